@@ -1,0 +1,122 @@
+"""FP64 CPU oracle for the second-order Trotter-Suzuki step (Sec. 2 of the paper).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``; never by the product package.  It
+shares no code with the HIP library.  ``tso_oracle.c`` holds the arithmetic;
+this module only marshals NumPy arrays into it.  ``closed_form.py`` holds the
+independent closed-form solutions used to pin it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tso_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "libtso_oracle.so")
+
+BC = {"periodic": 0, "closed": 1}
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle into oracle/_build/libtso_oracle.so (portable -O2, OpenMP)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    d, i, ll, p = ctypes.c_double, ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p
+    lib.tso_evolve.argtypes = [i, i, i, d, d, d, d, d, p, p, ll, i]
+    lib.tso_evolve.restype = i
+    lib.tso_apply_factor.argtypes = [i, i, i, d, d, d, d, i, i, d, p, p]
+    lib.tso_apply_factor.restype = i
+    lib.tso_observables.argtypes = [i, i, i, d, d, d, d, p, p,
+                                    ctypes.POINTER(d), ctypes.POINTER(d)]
+    lib.tso_observables.restype = i
+    lib.tso_set_threads.argtypes = [i]
+    lib.tso_set_threads.restype = None
+    lib.tso_max_threads.argtypes = []
+    lib.tso_max_threads.restype = i
+    _lib = lib
+    return lib
+
+
+def set_threads(n: int) -> None:
+    _load().tso_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().tso_max_threads())
+
+
+def _as_psi(psi) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    if a.ndim != 2:
+        raise ValueError("psi must be (ny, nx)")
+    return a.copy()
+
+
+def _as_v(V, shape) -> np.ndarray:
+    v = np.ascontiguousarray(np.asarray(V, dtype=np.float64))
+    if v.shape != shape:
+        raise ValueError(f"V shape {v.shape} != psi shape {shape}")
+    return v
+
+
+def evolve(psi0, V, dt, steps, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
+           bc="periodic", order=2) -> np.ndarray:
+    """Return psi after `steps` steps of U2(dt) (order=2) or U4(dt) (order=4)."""
+    psi = _as_psi(psi0)
+    v = _as_v(V, psi.shape)
+    ny, nx = psi.shape
+    rc = _load().tso_evolve(nx, ny, BC[bc], dx, dy, mass, hbar, dt,
+                            v.ctypes.data, psi.ctypes.data, int(steps), int(order))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return psi
+
+
+def apply_factor(psi0, V, which, parity, tau, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
+                 bc="periodic") -> np.ndarray:
+    """Apply one factor: which in {"x", "y", "P"}; parity 0 = even pairs, 1 = odd."""
+    psi = _as_psi(psi0)
+    ny, nx = psi.shape
+    v = _as_v(V if V is not None else np.zeros((ny, nx)), psi.shape)
+    w = {"x": 0, "y": 1, "P": 2}[which]
+    rc = _load().tso_apply_factor(nx, ny, BC[bc], dx, dy, mass, hbar, w, int(parity),
+                                  float(tau), v.ctypes.data, psi.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return psi
+
+
+def observables(psi, V, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0, bc="periodic"):
+    """Return (norm, energy) = (sum |psi|^2, <psi|H|psi>/norm)."""
+    a = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    v = _as_v(V, a.shape)
+    ny, nx = a.shape
+    n, e = ctypes.c_double(), ctypes.c_double()
+    rc = _load().tso_observables(nx, ny, BC[bc], dx, dy, mass, hbar, v.ctypes.data,
+                                 a.ctypes.data, ctypes.byref(n), ctypes.byref(e))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return n.value, e.value

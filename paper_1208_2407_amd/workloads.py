@@ -1,0 +1,248 @@
+"""Seeded synthetic inputs for the Trotter-Suzuki solver: meshes, potentials, states.
+
+This module holds input generation only (no step of the method).  The tests,
+the benchmark and the oracle-side checks all draw their inputs from here, so
+the HIP path and the oracle always see the same arrays.
+
+The paper benchmarks "a synthetic state" on a flat potential (Sec. 2 last
+paragraph; Sec. 4).  The workloads below follow that spirit with richer
+potentials so that the diagonal phase is exercised:
+
+* coordinates  x_i = (i - nx/2) dx,  y_j = (j - ny/2) dy  (origin at the centre);
+* Gaussian packet  exp(-((x-x0)^2 + (y-y0)^2) / (4 sigma^2) + i (kx x + ky y));
+  a superposition takes unit amplitudes with seeded phases and is normalised so
+  that sum |psi|^2 = 1 (the normalisation uses exact 1D Gram sums, so any
+  window of the mesh can be generated on its own with the global constant);
+* harmonic well  V = m omega^2 (x^2 + y^2) / 2;
+* bump  A exp(-|r - c|^2 / (2 w^2)),  A ~ U[-0.5, 0.5],  c uniform over the mesh.
+
+Every field is a sum of separable terms, so a mesh of any size is built from
+1D vectors with outer products (and one small matrix product for the bumps).
+Random numbers come from numpy PCG64(seed) in a fixed draw order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+
+@dataclasses.dataclass
+class Packet:
+    x0: float
+    y0: float
+    kx: float
+    ky: float
+    theta: float
+    sigma: float
+
+
+@dataclasses.dataclass
+class Bump:
+    amp: float
+    cx: float
+    cy: float
+    width: float
+
+
+@dataclasses.dataclass
+class Problem:
+    """One solve: mesh, constants, time step, step count and the input recipe."""
+    name: str
+    nx: int
+    ny: int
+    dt: float
+    steps: int
+    dtype: str = "c128"          # "c128" or "c64"
+    dx: float = 1.0
+    dy: float = 1.0
+    mass: float = 1.0
+    hbar: float = 1.0
+    bc: str = "periodic"
+    omega: float = 0.0
+    packets: List[Packet] = dataclasses.field(default_factory=list)
+    bumps: List[Bump] = dataclasses.field(default_factory=list)
+    v0: float = 0.0              # constant offset added to the potential
+
+    @property
+    def sites(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def site_steps(self) -> int:
+        return self.nx * self.ny * self.steps
+
+
+# ---------------------------------------------------------------- recipe draws
+
+def _even(v: float, lo: int) -> int:
+    n = int(round(v / 2.0)) * 2
+    return max(lo, n)
+
+
+def _draw_packets(rng: np.random.Generator, n: int, Lx: float, Ly: float, frac: float,
+                  sigma: float) -> List[Packet]:
+    out = []
+    for _ in range(n):
+        x0 = rng.uniform(-frac * Lx, frac * Lx)
+        y0 = rng.uniform(-frac * Ly, frac * Ly)
+        kx = rng.uniform(-0.5, 0.5)
+        ky = rng.uniform(-0.5, 0.5)
+        th = rng.uniform(0.0, 2.0 * math.pi)
+        out.append(Packet(x0, y0, kx, ky, th, sigma))
+    return out
+
+
+def _draw_bumps(rng: np.random.Generator, n: int, Lx: float, Ly: float,
+                width: float) -> List[Bump]:
+    out = []
+    for _ in range(n):
+        a = rng.uniform(-0.5, 0.5)
+        cx = rng.uniform(-0.5 * Lx, 0.5 * Lx)
+        cy = rng.uniform(-0.5 * Ly, 0.5 * Ly)
+        out.append(Bump(a, cx, cy, width))
+    return out
+
+
+def gaussian_in_well(n: int = 256, seed: int = 1, dt: float = 0.1, steps: int = 100,
+                     dtype: str = "c128") -> Problem:
+    """One packet (sigma = 16 sites, centred, seeded momentum in [-0.5, 0.5]^2)
+    in a harmonic well omega = 0.01; hbar = m = dx = 1.  Default: 256^2,
+    dt = 0.1, 100 steps, complex128."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kx, ky = rng.uniform(-0.5, 0.5, size=2)
+    p = Packet(0.0, 0.0, float(kx), float(ky), 0.0, 16.0)
+    return Problem(f"gaussian_in_well_{n}", n, n, dt, steps, dtype, omega=0.01, packets=[p])
+
+
+def packets_and_bumps(nx: int, ny: int, seed: int, dt: float, steps: int, dtype: str,
+                      n_packets: int = 4, scale: float = 1.0, name: str = "") -> Problem:
+    """Four seeded packets (sigma = 16, centres in the central [-L/8, L/8]^2,
+    momenta in [-0.5, 0.5]^2) in a harmonic well plus 32 seeded Gaussian bumps.
+    `scale` stretches the recipe's lengths: omega = 0.01 / scale, bump width
+    64 * scale (scale = L / 4096 reproduces the 4096^2 recipe on another mesh)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    packets = _draw_packets(rng, n_packets, float(nx), float(ny), 0.125, 16.0)
+    bumps = _draw_bumps(rng, 32, float(nx), float(ny), 64.0 * scale)
+    return Problem(name or f"packets_bumps_{nx}x{ny}", nx, ny, dt, steps, dtype,
+                   omega=0.01 / scale, packets=packets, bumps=bumps)
+
+
+def config(name: str) -> Problem:
+    """The named single-mesh workloads."""
+    if name == "well256":
+        return gaussian_in_well()
+    if name == "mesh4096_c128":
+        return packets_and_bumps(4096, 4096, 2, 0.05, 1000, "c128", name=name)
+    if name == "mesh4096_c64":
+        return packets_and_bumps(4096, 4096, 2, 0.05, 1000, "c64", name=name)
+    if name == "mesh32768_c64":
+        return packets_and_bumps(32768, 32768, 3, 0.05, 200, "c64", scale=32768 / 4096,
+                                 name=name)
+    raise KeyError(name)
+
+
+def batch_problems(count: int = 512, seed: int = 4, steps: int = 500, lo: int = 64,
+                   hi: int = 1024, dtype: str = "c64") -> List[Problem]:
+    """Independent problems with sides log-uniform in [lo, hi] rounded to even
+    (square with probability 1/2, else two independent draws), each with its
+    own packets-and-bumps recipe and dt drawn from {0.02, 0.05, 0.1}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        square = rng.uniform() < 0.5
+        a = _even(math.exp(rng.uniform(math.log(lo), math.log(hi))), lo)
+        b = a if square else _even(math.exp(rng.uniform(math.log(lo), math.log(hi))), lo)
+        dt = float(rng.choice([0.02, 0.05, 0.1]))
+        sub_seed = int(rng.integers(0, 2**31 - 1))
+        p = packets_and_bumps(a, b, sub_seed, dt, steps, dtype, name=f"batch{i}_{a}x{b}")
+        out.append(p)
+    return out
+
+
+# ---------------------------------------------------------------- fields
+
+def _coords(n: int, d: float, lo: int, hi: int) -> np.ndarray:
+    return (np.arange(lo, hi, dtype=np.float64) - n / 2) * d
+
+
+def _packet_1d(x: np.ndarray, x0: float, k: float, sigma: float) -> np.ndarray:
+    return np.exp(-((x - x0) ** 2) / (4.0 * sigma * sigma) + 1j * k * x)
+
+
+def state_norm2(p: Problem) -> float:
+    """sum |sum_k a_k f_k(x) g_k(y)|^2 over the full mesh, from 1D Gram sums."""
+    xs = _coords(p.nx, p.dx, 0, p.nx)
+    ys = _coords(p.ny, p.dy, 0, p.ny)
+    F = np.stack([_packet_1d(xs, q.x0, q.kx, q.sigma) for q in p.packets])  # (K, nx)
+    G = np.stack([_packet_1d(ys, q.y0, q.ky, q.sigma) for q in p.packets])
+    a = np.array([np.exp(1j * q.theta) for q in p.packets])
+    Gx = np.conj(F) @ F.T       # Gx[k, l] = sum_x conj(f_k) f_l
+    Gy = np.conj(G) @ G.T
+    n2 = np.einsum("k,l,kl,kl->", np.conj(a), a, Gx, Gy)
+    return float(n2.real)
+
+
+def initial_state(p: Problem, device="cpu", dtype=torch.complex128,
+                  rows: Optional[Tuple[int, int]] = None,
+                  cols: Optional[Tuple[int, int]] = None,
+                  chunk_rows: int = 2048) -> torch.Tensor:
+    """psi_0 on rows [r0, r1) x cols [c0, c1) of the mesh (default: all), normalised
+    over the whole mesh, as a contiguous tensor of `dtype` on `device`."""
+    r0, r1 = rows if rows is not None else (0, p.ny)
+    c0, c1 = cols if cols is not None else (0, p.nx)
+    inv = 1.0 / math.sqrt(state_norm2(p))
+    xs = _coords(p.nx, p.dx, c0, c1)
+    ys = _coords(p.ny, p.dy, r0, r1)
+    F = torch.from_numpy(np.stack([_packet_1d(xs, q.x0, q.kx, q.sigma) for q in p.packets]))
+    a = np.array([np.exp(1j * q.theta) * inv for q in p.packets])
+    G = np.stack([_packet_1d(ys, q.y0, q.ky, q.sigma) for q in p.packets]) * a[:, None]
+    G = torch.from_numpy(np.ascontiguousarray(G.T))          # (rows, K)
+    F = F.to(device)
+    out = torch.empty((r1 - r0, c1 - c0), dtype=dtype, device=device)
+    for s in range(0, r1 - r0, chunk_rows):
+        e = min(r1 - r0, s + chunk_rows)
+        out[s:e] = (G[s:e].to(device) @ F).to(dtype)
+    return out
+
+
+def potential(p: Problem, device="cpu", rows: Optional[Tuple[int, int]] = None,
+              cols: Optional[Tuple[int, int]] = None, chunk_rows: int = 2048) -> torch.Tensor:
+    """V on rows [r0, r1) x cols [c0, c1) as contiguous float64 on `device`."""
+    r0, r1 = rows if rows is not None else (0, p.ny)
+    c0, c1 = cols if cols is not None else (0, p.nx)
+    xs = _coords(p.nx, p.dx, c0, c1)
+    ys = _coords(p.ny, p.dy, r0, r1)
+    k = 0.5 * p.mass * p.omega * p.omega
+    vx = torch.from_numpy(k * xs * xs + p.v0).to(device)
+    vy = torch.from_numpy(k * ys * ys).to(device)
+    nb = len(p.bumps)
+    out = torch.empty((r1 - r0, c1 - c0), dtype=torch.float64, device=device)
+    if nb:
+        U = np.stack([np.exp(-((xs - b.cx) ** 2) / (2 * b.width ** 2)) for b in p.bumps])
+        W = np.stack([b.amp * np.exp(-((ys - b.cy) ** 2) / (2 * b.width ** 2))
+                      for b in p.bumps])
+        U = torch.from_numpy(U).to(device)
+        W = torch.from_numpy(np.ascontiguousarray(W.T))
+    for s in range(0, r1 - r0, chunk_rows):
+        e = min(r1 - r0, s + chunk_rows)
+        blk = vy[s:e, None] + vx[None, :]
+        if nb:
+            blk = blk + W[s:e].to(device) @ U
+        out[s:e] = blk
+    return out
+
+
+def random_state(nx: int, ny: int, seed: int) -> np.ndarray:
+    """Unit-norm complex Gaussian noise: a state with every wavenumber present."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    return a / np.linalg.norm(a)
+
+
+def random_potential(nx: int, ny: int, seed: int, scale: float = 1.0) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return scale * rng.standard_normal((ny, nx))

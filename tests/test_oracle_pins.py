@@ -1,0 +1,278 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's rotation formula: each compares it with an
+independent construction (dense matrix exponentials of the split Hamiltonian,
+exact diagonalisation, the Bloch closed form, exact invariants or brute force).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_form as cf
+from paper_1208_2407_amd import workloads as wl
+from tests import _dense as dense
+
+ANISO = dict(dx=1.3, dy=0.8, mass=1.7, hbar=0.9)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def setup_module(_):
+    oracle.build(force=False)
+
+
+# ---------------------------------------------------------------- P1: operator identity
+
+@pytest.mark.parametrize("shape,bc", [((4, 4), "periodic"), ((6, 4), "periodic"),
+                                      ((8, 6), "periodic"), ((2, 4), "periodic"),
+                                      ((4, 2), "periodic"), ((5, 3), "closed"),
+                                      ((7, 4), "closed"), ((2, 2), "closed")])
+@pytest.mark.parametrize("which,parity", [("x", 0), ("x", 1), ("y", 0), ("y", 1), ("P", 0)])
+def test_single_factor_equals_dense_expm(shape, bc, which, parity):
+    """Each factor is exp(-i tau H_k / hbar) of the paper's block matrix (Sec. 2)."""
+    nx, ny = shape
+    V = wl.random_potential(nx, ny, 11)
+    psi = wl.random_state(nx, ny, 12)
+    tau = 0.37
+    got = oracle.apply_factor(psi, V, which, parity, tau, bc=bc, **ANISO)
+    p = dense.parts(nx, ny, V, bc=bc, **ANISO)
+    key = {"x": ["Ex", "Ox"], "y": ["Ey", "Oy"]}.get(which, ["H0", "H0"])[parity]
+    U = dense.factor(p[key], tau, ANISO["hbar"])
+    want = (U @ psi.reshape(-1)).reshape(ny, nx)
+    assert rel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("shape,bc", [((4, 4), "periodic"), ((6, 4), "periodic"),
+                                      ((8, 6), "periodic"), ((2, 4), "periodic"),
+                                      ((5, 3), "closed"), ((6, 5), "closed")])
+def test_step_equals_dense_factor_product(shape, bc):
+    """N steps of the oracle = (product of the nine dense factors)^N."""
+    nx, ny = shape
+    V = wl.random_potential(nx, ny, 21)
+    psi = wl.random_state(nx, ny, 22)
+    dt, N = 0.21, 5
+    got = oracle.evolve(psi, V, dt, N, bc=bc, **ANISO)
+    U = np.linalg.matrix_power(dense.u2_dense(nx, ny, V, dt, bc=bc, **ANISO), N)
+    want = (U @ psi.reshape(-1)).reshape(ny, nx)
+    assert rel(got, want) < 1e-13
+
+
+# ---------------------------------------------------------------- P2: second order
+
+@pytest.mark.parametrize("shape,bc", [((6, 4), "periodic"), ((8, 6), "periodic"),
+                                      ((5, 4), "closed")])
+def test_error_shrinks_as_dt_squared(shape, bc):
+    """At fixed t the error against exp(-iHt/hbar) falls 4x per halving of dt (A5, A13)."""
+    nx, ny = shape
+    V = wl.random_potential(nx, ny, 31)
+    psi = wl.random_state(nx, ny, 32)
+    t = 1.0
+    exact = (dense.exact_evolution(nx, ny, V, t, bc=bc, **ANISO) @ psi.reshape(-1)).reshape(ny, nx)
+    errs = []
+    for N in (8, 16, 32, 64):
+        got = oracle.evolve(psi, V, t / N, N, bc=bc, **ANISO)
+        errs.append(rel(got, exact))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    for r in ratios:
+        assert abs(r - 4.0) < 0.1, (errs, ratios)
+
+
+def test_fourth_order_error_shrinks_sixteenfold():
+    """U4 of Eq. "fourthorder": error falls 16x per halving of dt."""
+    nx, ny = 6, 4
+    V = wl.random_potential(nx, ny, 33)
+    psi = wl.random_state(nx, ny, 34)
+    t = 1.0
+    exact = (dense.exact_evolution(nx, ny, V, t, **ANISO) @ psi.reshape(-1)).reshape(ny, nx)
+    errs = [rel(oracle.evolve(psi, V, t / N, N, order=4, **ANISO), exact) for N in (4, 8, 16)]
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    for r in ratios:
+        assert 14.5 < r < 17.5, (errs, ratios)
+
+
+# ---------------------------------------------------------------- P3: Bloch closed form
+
+@pytest.mark.parametrize("shape,N", [((16, 16), 7), ((32, 24), 13), ((8, 40), 3)])
+def test_bloch_closed_form(shape, N):
+    nx, ny = shape
+    psi = wl.random_state(nx, ny, 41)
+    V0 = 0.37
+    V = np.full((ny, nx), V0)
+    got = oracle.evolve(psi, V, 0.17, N, **ANISO)
+    want = cf.bloch_evolve(psi, V0, 0.17, N, **ANISO)
+    assert rel(got, want) < 1e-13
+
+
+# ---------------------------------------------------------------- P4/P5: invariants
+
+def test_norm_conserved_over_long_runs():
+    p = wl.gaussian_in_well(n=64, steps=2000)
+    psi0 = wl.initial_state(p).numpy()
+    V = wl.potential(p).numpy()
+    out = oracle.evolve(psi0, V, p.dt, p.steps)
+    n0 = np.sum(np.abs(psi0) ** 2)
+    n1 = np.sum(np.abs(out) ** 2)
+    assert abs(n1 - n0) < 1e-13
+
+
+@pytest.mark.parametrize("bc", ["periodic", "closed"])
+def test_forward_then_backward_is_identity(bc):
+    nx, ny = (20, 14)
+    V = wl.random_potential(nx, ny, 51)
+    psi = wl.random_state(nx, ny, 52)
+    fwd = oracle.evolve(psi, V, 0.3, 40, bc=bc, **ANISO)
+    back = oracle.evolve(fwd, V, -0.3, 40, bc=bc, **ANISO)
+    assert rel(back, psi) < 1e-13
+    # U2(dt)^-1 = conj(U2(dt)) conj: every part of H is real and the product palindromic
+    back2 = np.conj(oracle.evolve(np.conj(fwd), V, 0.3, 40, bc=bc, **ANISO))
+    assert rel(back2, psi) < 1e-13
+
+
+# ---------------------------------------------------------------- P6: separability
+
+def _one_d_u2(L, v, dt, a, mass, hbar, bc="periodic"):
+    """Dense 1D step: hop on even and odd pairs, diagonal v + hbar^2/(m a^2)."""
+    J = hbar * hbar / (2 * mass * a * a)
+    He = dense.hop_matrix(L, 1, "x", 0, J, bc)
+    Ho = dense.hop_matrix(L, 1, "x", 1, J, bc)
+    H0 = np.diag(v + 2 * J)
+    fe, fo = dense.factor(He, dt / 2, hbar), dense.factor(Ho, dt / 2, hbar)
+    P = dense.factor(H0, dt, hbar)
+    return fo @ fe @ P @ fe @ fo
+
+
+def test_separable_problem_is_outer_product_of_1d_runs():
+    nx, ny, N, dt = 256, 128, 20, 0.13
+    rng = np.random.Generator(np.random.PCG64(61))
+    vx = rng.standard_normal(nx) * 0.5
+    vy = rng.standard_normal(ny) * 0.5
+    f = rng.standard_normal(nx) + 1j * rng.standard_normal(nx)
+    g = rng.standard_normal(ny) + 1j * rng.standard_normal(ny)
+    V = vy[:, None] + vx[None, :]
+    psi = np.outer(g, f)
+    psi /= np.linalg.norm(psi)
+    got = oracle.evolve(psi, V, dt, N, **ANISO)
+    # the 2D diagonal splits as (vx + 2Jx) + (vy + 2Jy)
+    Ux = np.linalg.matrix_power(_one_d_u2(nx, vx, dt, ANISO["dx"], ANISO["mass"], ANISO["hbar"]), N)
+    Uy = np.linalg.matrix_power(_one_d_u2(ny, vy, dt, ANISO["dy"], ANISO["mass"], ANISO["hbar"]), N)
+    want = np.outer(Uy @ g, Ux @ f) / np.linalg.norm(np.outer(g, f))
+    assert rel(got, want) < 1e-13
+
+
+# ---------------------------------------------------------------- P7: light cone
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 10])
+@pytest.mark.parametrize("x0", [46, 47])
+def test_light_cone(N, x0):
+    """A delta at an even site reaches [-(2N+1), 2N]; at an odd site [-2N, 2N+1]."""
+    nx, ny = 96, 96
+    psi = np.zeros((ny, nx), complex)
+    y0 = 44 + (x0 % 2)
+    psi[y0, x0] = 1.0
+    V = wl.random_potential(nx, ny, 71)
+    out = oracle.evolve(psi, V, 0.2, N)
+    ys, xs = np.nonzero(out)
+    lo, hi = (-(2 * N + 1), 2 * N) if x0 % 2 == 0 else (-2 * N, 2 * N + 1)
+    assert xs.min() - x0 == lo and xs.max() - x0 == hi
+    lo_y, hi_y = (-(2 * N + 1), 2 * N) if y0 % 2 == 0 else (-2 * N, 2 * N + 1)
+    assert ys.min() - y0 == lo_y and ys.max() - y0 == hi_y
+
+
+# ---------------------------------------------------------------- P8: translation by two sites
+
+def test_two_site_translation():
+    nx, ny = 24, 18
+    V = wl.random_potential(nx, ny, 81)
+    psi = wl.random_state(nx, ny, 82)
+    out = oracle.evolve(psi, V, 0.25, 9)
+    sh = (4, -6)
+    out2 = oracle.evolve(np.roll(psi, sh, axis=(0, 1)), np.roll(V, sh, axis=(0, 1)), 0.25, 9)
+    np.testing.assert_array_equal(out2, np.roll(out, sh, axis=(0, 1)))
+
+
+# ---------------------------------------------------------------- P9: special cases
+
+def test_zero_steps_and_zero_dt_are_identity():
+    nx, ny = 10, 8
+    V = wl.random_potential(nx, ny, 91)
+    psi = wl.random_state(nx, ny, 92)
+    np.testing.assert_array_equal(oracle.evolve(psi, V, 0.3, 0), psi)
+    np.testing.assert_array_equal(oracle.evolve(psi, V, 0.0, 7), psi)
+
+
+def test_constant_potential_is_global_phase():
+    nx, ny = 12, 10
+    psi = wl.random_state(nx, ny, 93)
+    V0, dt, N = 0.71, 0.19, 11
+    flat = oracle.evolve(psi, np.zeros((ny, nx)), dt, N, **ANISO)
+    shifted = oracle.evolve(psi, np.full((ny, nx), V0), dt, N, **ANISO)
+    want = flat * np.exp(-1j * N * dt * V0 / ANISO["hbar"])
+    assert rel(shifted, want) < 1e-14
+
+
+def test_linearity():
+    nx, ny = 12, 10
+    V = wl.random_potential(nx, ny, 94)
+    a, b = wl.random_state(nx, ny, 95), wl.random_state(nx, ny, 96)
+    al, be = 0.3 - 0.7j, 1.1 + 0.2j
+    lhs = oracle.evolve(al * a + be * b, V, 0.2, 6)
+    rhs = al * oracle.evolve(a, V, 0.2, 6) + be * oracle.evolve(b, V, 0.2, 6)
+    assert rel(lhs, rhs) < 1e-14
+
+
+# ---------------------------------------------------------------- P10: observables
+
+@pytest.mark.parametrize("m", [(0, 0), (3, 1), (-5, 7), (8, 6)])
+def test_plane_wave_energy(m):
+    nx, ny = 16, 12
+    V0 = 0.4
+    psi = cf.plane_wave(nx, ny, *m)
+    n, e = oracle.observables(psi, np.full((ny, nx), V0), **ANISO)
+    assert abs(n - 1.0) < 1e-14
+    assert abs(e - cf.plane_wave_energy(nx, ny, *m, V0, **ANISO)) < 1e-14
+
+
+@pytest.mark.parametrize("shape,bc", [((6, 4), "periodic"), ((2, 4), "periodic"),
+                                      ((5, 3), "closed")])
+def test_energy_equals_dense_expectation(shape, bc):
+    nx, ny = shape
+    V = wl.random_potential(nx, ny, 101)
+    psi = wl.random_state(nx, ny, 102) * 1.7
+    n, e = oracle.observables(psi, V, bc=bc, **ANISO)
+    H = dense.full_h(nx, ny, V, bc=bc, **ANISO)
+    v = psi.reshape(-1)
+    assert abs(n - np.vdot(v, v).real) < 1e-13
+    assert abs(e - (np.vdot(v, H @ v) / np.vdot(v, v)).real) < 1e-13
+
+
+# ---------------------------------------------------------------- argument handling, threads
+
+def test_rejects_bad_arguments():
+    psi = wl.random_state(6, 4, 1)
+    V = np.zeros((4, 6))
+    with pytest.raises(ValueError):
+        oracle.evolve(wl.random_state(5, 4, 1), np.zeros((4, 5)), 0.1, 1)   # odd periodic side
+    with pytest.raises(ValueError):
+        oracle.evolve(psi, V, float("nan"), 1)
+    with pytest.raises(ValueError):
+        oracle.evolve(psi, V, 0.1, 1, mass=0.0)
+    with pytest.raises(ValueError):
+        oracle.evolve(psi, V, 0.1, -1)
+
+
+def test_thread_count_does_not_change_results():
+    p = wl.gaussian_in_well(n=64, steps=30)
+    psi0 = wl.initial_state(p).numpy()
+    V = wl.potential(p).numpy()
+    nthreads = oracle.max_threads()
+    oracle.set_threads(1)
+    a = oracle.evolve(psi0, V, p.dt, p.steps)
+    na = oracle.observables(a, V)
+    oracle.set_threads(max(2, nthreads))
+    b = oracle.evolve(psi0, V, p.dt, p.steps)
+    nb = oracle.observables(b, V)
+    oracle.set_threads(nthreads)
+    np.testing.assert_array_equal(a, b)
+    assert na == nb
