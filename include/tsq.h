@@ -1,0 +1,154 @@
+/*
+ * tsq.h — C ABI of the MI355X (gfx950) second-order Trotter-Suzuki solver.
+ *
+ * The library evolves one quantum particle on a 2D real-space mesh with the
+ * second-order Trotter-Suzuki product of Wittek & Cucchietti, "A Second-Order
+ * Distributed Trotter-Suzuki Solver with a Hybrid Kernel" (Sec. 2).  The
+ * calls follow the paper's statement of the problem: a mesh of spacing a
+ * (Sec. 2, the finite-mesh discretisation), particle mass m and hbar (the
+ * Hamiltonian -hbar^2/(2m) d^2/dx^2 + V(x)), the external potential V, the
+ * initial state |psi(0)> (Sec. 2, Eq. "evolution"), the time step dt and a
+ * number of steps (Sec. 2, the first-order factor U1(dt) and its symmetrised
+ * second-order product, Eq. "secondorder").
+ *
+ * Conventions
+ *   - Mesh: nx * ny sites, row-major (y, x), x fastest.  psi is interleaved
+ *     complex: complex128 = two doubles (re, im) per site, complex64 = two
+ *     floats.  V is one double per site.
+ *   - One step is U2(dt) = exp(-i dt H / hbar) + O(dt^3) applied as
+ *       Ox(h) Oy(h) Ex(h) Ey(h) P(dt) Ey(h) Ex(h) Oy(h) Ox(h),  h = dt/2,
+ *     (first factor applied first) where Ea/Oa rotate the even pairs
+ *     (2j, 2j+1) / odd pairs (2j+1, 2j+2) of every line along axis a by the
+ *     2x2 block exponential [[cos al, i sin al], [i sin al, cos al]],
+ *     al = tau hbar / (2 m da^2), and P multiplies site l by
+ *     exp(-i dt (V_l + hbar^2/(m dx^2) + hbar^2/(m dy^2)) / hbar).
+ *     Consecutive steps share their odd factors (Ox(h)Ox(h) = Ox(2h)); one
+ *     tsq_evolve call therefore applies exactly U2(dt)^steps up to rounding.
+ *   - Periodic boundaries: the odd pairs include (L-1, 0); both sides must be
+ *     even.  Closed boundaries (hard walls, no wrap pair) are declared for a
+ *     later version and currently return TSQ_ERR_UNSUPPORTED.
+ *
+ * Memory and ownership
+ *   - The caller owns all device memory: psi, V, and a workspace of
+ *     tsq_workspace_size() bytes (second psi buffer, phase table, reduction
+ *     scratch).  The library never allocates or frees device memory and keeps
+ *     no device pointer between calls except the workspace address recorded by
+ *     tsq_set_potential, which later calls must pass again.
+ *   - A plan is host memory owned by the caller (create / destroy).  Plans are
+ *     not thread-safe: one thread at a time may use a plan.
+ *
+ * Streams and errors
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call is asynchronous on that stream except tsq_observables, which
+ *     synchronises it to return host values.
+ *   - Every function returns a tsq_status; nothing throws or aborts across the
+ *     ABI.  Arguments are validated on the host before any launch: a rejected
+ *     call launches nothing and leaves every buffer untouched.  A HIP launch
+ *     failure is TSQ_ERR_DEVICE with the HIP error string in tsq_last_error().
+ *     Asynchronous device faults surface at the next synchronising call.
+ */
+#ifndef TSQ_H
+#define TSQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSQ_ABI_VERSION 1
+
+typedef enum {
+    TSQ_OK = 0,
+    TSQ_ERR_ARG = -1,         /* null pointer, non-finite or non-positive constant, bad count */
+    TSQ_ERR_SHAPE = -2,       /* side < 2, odd side under periodic boundaries, too many sites */
+    TSQ_ERR_DTYPE = -3,       /* unknown dtype */
+    TSQ_ERR_WORKSPACE = -4,   /* workspace too small or misaligned */
+    TSQ_ERR_DEVICE = -5,      /* a HIP call failed; see tsq_last_error() */
+    TSQ_ERR_STATE = -6,       /* call out of order (e.g. evolve before set_potential, other ws) */
+    TSQ_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+} tsq_status;
+
+typedef enum { TSQ_C64 = 0, TSQ_C128 = 1 } tsq_dtype;
+typedef enum { TSQ_BC_PERIODIC = 0, TSQ_BC_CLOSED = 1 } tsq_bc;
+
+/* The problem statement of Sec. 2: mesh, spacing, mass, hbar, time step. */
+typedef struct {
+    int32_t nx, ny;   /* sites along x and y; >= 2, even under periodic boundaries */
+    double dx, dy;    /* mesh spacing a along each axis; finite, > 0 */
+    double mass;      /* particle mass m; finite, > 0 */
+    double hbar;      /* reduced Planck constant; finite, > 0 */
+    double dt;        /* time step; finite, any sign (negative evolves backwards) */
+    int32_t bc;       /* tsq_bc */
+    int32_t dtype;    /* tsq_dtype of psi */
+} tsq_problem;
+
+typedef struct tsq_plan tsq_plan; /* opaque, host memory */
+
+/* Version of this ABI (TSQ_ABI_VERSION of the library that was loaded). */
+int tsq_abi_version(void);
+
+/* Message of the last failed call on the calling thread ("" if none).  The
+ * pointer stays valid until the next tsq_* call on the same thread. */
+const char* tsq_last_error(void);
+
+/* Validate a problem and build a plan: the FP64 rotation coefficients
+ * (sin al and 1 - cos al = 2 sin^2(al/2) for tau = dt/2 and dt along each
+ * axis) and a default schedule.  Host only; touches no device.
+ * Errors: TSQ_ERR_ARG (null, bad constant), TSQ_ERR_SHAPE, TSQ_ERR_DTYPE,
+ * TSQ_ERR_UNSUPPORTED (closed boundaries).  *out is set only on TSQ_OK. */
+int tsq_plan_create(const tsq_problem* problem, tsq_plan** out);
+
+/* Free a plan (NULL is accepted). */
+int tsq_plan_destroy(tsq_plan* plan);
+
+/* Bytes of device workspace the plan needs: a second psi buffer, the phase
+ * table (complex128: one complex double per site; complex64: a hi/lo pair of
+ * complex floats per site) and reduction scratch.  Host only. */
+int tsq_workspace_size(const tsq_plan* plan, size_t* bytes);
+
+/* Schedule of the fused step kernel: `steps_per_pass` time steps per read and
+ * write of psi in device memory (1..4; 0 = library default), `segment_rows`
+ * rows marched by one wavefront (even; 0 = default) and `pairs_per_lane`
+ * x-pairs held by each lane (1 or 2; 0 = default).  Every schedule applies
+ * the same operations in the same order to every site, so results are
+ * bitwise identical across schedules.  get returns the values in force
+ * (defaults resolved; segment_rows 0 means "sized per pass").
+ * Host only.  Errors: TSQ_ERR_ARG. */
+int tsq_plan_set_schedule(tsq_plan* plan, int32_t steps_per_pass, int32_t segment_rows,
+                          int32_t pairs_per_lane);
+int tsq_plan_get_schedule(const tsq_plan* plan, int32_t* steps_per_pass, int32_t* segment_rows,
+                          int32_t* pairs_per_lane);
+
+/* Row a0: build the phase table exp(-i dt (V_l + eps0) / hbar) in FP64 from
+ * the device array V_dev (nx*ny doubles) into the workspace `ws` of
+ * `ws_bytes` bytes (device, 256-byte aligned), rounded to the plan's dtype.
+ * Records `ws`; tsq_evolve must be given the same workspace.
+ * Errors: TSQ_ERR_ARG (null), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
+int tsq_set_potential(tsq_plan* plan, const double* V_dev, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Rows a1-a6: apply U2(dt)^steps to psi_dev in place (device, contiguous,
+ * 16-byte aligned).  steps == 0 returns TSQ_OK without a launch.
+ * Errors: TSQ_ERR_ARG (null, steps < 0, misaligned psi), TSQ_ERR_STATE (no
+ * potential set, or a different workspace), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
+int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws_bytes,
+               void* stream);
+
+/* Row a7: FP64 norm N = sum |psi_l|^2 and energy E = <psi|H|psi> / N of the
+ * lattice Hamiltonian H = diag(V + eps0) - Jx (x-neighbours) - Jy
+ * (y-neighbours), J_a = hbar^2/(2 m da^2), neighbours wrapping periodically.
+ * Reduces in a fixed order (bitwise reproducible), uses the scratch part of
+ * `ws` (it does not disturb the phase table), synchronises `stream` and
+ * writes the two host doubles.  Errors: TSQ_ERR_ARG, TSQ_ERR_WORKSPACE,
+ * TSQ_ERR_DEVICE. */
+int tsq_observables(const tsq_plan* plan, const void* psi_dev, const double* V_dev,
+                    double* norm_out, double* energy_out, void* ws, size_t ws_bytes,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSQ_H */

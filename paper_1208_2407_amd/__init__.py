@@ -1,1 +1,257 @@
-"""Second-order Trotter-Suzuki solver for AMD MI355X (gfx950)."""
+"""Second-order Trotter-Suzuki solver for one particle on a 2D mesh, for AMD MI355X.
+
+Thin Python binding of ``libtsq.so`` (C ABI in ``include/tsq.h``): every
+function named ``tsq_*`` here marshals its arguments into the C call of the
+same name and raises :class:`TsqError` on a non-zero status.  All arithmetic
+runs in the HIP kernels; torch is used only to own device memory and to hand
+over the current HIP stream.  There is no CPU fallback: if the library is not
+built, or no GPU is present, the calls fail loudly.
+
+Convenience layer: :class:`Plan` (one problem statement) and the functions
+:func:`evolve` and :func:`observables`.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libtsq.so")
+
+TSQ_OK = 0
+STATUS = {0: "TSQ_OK", -1: "TSQ_ERR_ARG", -2: "TSQ_ERR_SHAPE", -3: "TSQ_ERR_DTYPE",
+          -4: "TSQ_ERR_WORKSPACE", -5: "TSQ_ERR_DEVICE", -6: "TSQ_ERR_STATE",
+          -7: "TSQ_ERR_UNSUPPORTED"}
+DTYPES = {"c64": 0, "c128": 1}
+BCS = {"periodic": 0, "closed": 1}
+
+EXPORTED = ("tsq_abi_version", "tsq_last_error", "tsq_plan_create", "tsq_plan_destroy",
+            "tsq_workspace_size", "tsq_plan_set_schedule", "tsq_plan_get_schedule",
+            "tsq_set_potential", "tsq_evolve", "tsq_observables")
+
+
+class TsqError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class tsq_problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("mass", ctypes.c_double), ("hbar", ctypes.c_double),
+                ("dt", ctypes.c_double), ("bc", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libtsq.so (built in-tree by ``python -m paper_1208_2407_amd.build``)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libtsq.so is not built ({p}); run `python -m paper_1208_2407_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, sz, i32, i64, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.tsq_abi_version.argtypes = []
+    lib.tsq_abi_version.restype = ctypes.c_int
+    lib.tsq_last_error.argtypes = []
+    lib.tsq_last_error.restype = ctypes.c_char_p
+    lib.tsq_plan_create.argtypes = [ctypes.POINTER(tsq_problem), ctypes.POINTER(vp)]
+    lib.tsq_plan_destroy.argtypes = [vp]
+    lib.tsq_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.tsq_plan_set_schedule.argtypes = [vp, i32, i32, i32]
+    lib.tsq_plan_get_schedule.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                          ctypes.POINTER(i32)]
+    lib.tsq_set_potential.argtypes = [vp, vp, vp, sz, vp]
+    lib.tsq_evolve.argtypes = [vp, vp, i64, vp, sz, vp]
+    lib.tsq_observables.argtypes = [vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d), vp, sz, vp]
+    for name in EXPORTED[2:]:
+        getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != TSQ_OK:
+        raise TsqError(rc, load_library().tsq_last_error().decode())
+
+
+# ---------------------------------------------------------------- C-ABI mirrors
+
+def tsq_abi_version() -> int:
+    return load_library().tsq_abi_version()
+
+
+def tsq_last_error() -> str:
+    return load_library().tsq_last_error().decode()
+
+
+def tsq_plan_create(problem: tsq_problem) -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().tsq_plan_create(ctypes.byref(problem), ctypes.byref(h)))
+    return h.value
+
+
+def tsq_plan_destroy(plan: int) -> None:
+    _check(load_library().tsq_plan_destroy(plan))
+
+
+def tsq_workspace_size(plan: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().tsq_workspace_size(plan, ctypes.byref(n)))
+    return n.value
+
+
+def tsq_plan_set_schedule(plan: int, steps_per_pass: int, segment_rows: int,
+                          pairs_per_lane: int = 0) -> None:
+    _check(load_library().tsq_plan_set_schedule(plan, int(steps_per_pass), int(segment_rows),
+                                                int(pairs_per_lane)))
+
+
+def tsq_plan_get_schedule(plan: int) -> Tuple[int, int, int]:
+    s, r, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().tsq_plan_get_schedule(plan, ctypes.byref(s), ctypes.byref(r),
+                                                ctypes.byref(p)))
+    return s.value, r.value, p.value
+
+
+def tsq_set_potential(plan: int, V_dev: int, ws: int, ws_bytes: int, stream: int) -> None:
+    _check(load_library().tsq_set_potential(plan, V_dev, ws, ws_bytes, stream))
+
+
+def tsq_evolve(plan: int, psi_dev: int, steps: int, ws: int, ws_bytes: int, stream: int) -> None:
+    _check(load_library().tsq_evolve(plan, psi_dev, int(steps), ws, ws_bytes, stream))
+
+
+def tsq_observables(plan: int, psi_dev: int, V_dev: int, ws: int, ws_bytes: int,
+                    stream: int) -> Tuple[float, float]:
+    n, e = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().tsq_observables(plan, psi_dev, V_dev, ctypes.byref(n), ctypes.byref(e),
+                                          ws, ws_bytes, stream))
+    return n.value, e.value
+
+
+# ---------------------------------------------------------------- convenience layer
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """One problem statement (mesh, spacing, mass, hbar, dt, dtype) with its workspace.
+
+    The workspace (second psi buffer, phase table, reduction scratch) is a
+    torch uint8 tensor on the plan's device; :meth:`set_potential` must be
+    called before :meth:`evolve`.
+    """
+
+    def __init__(self, nx: int, ny: int, dt: float, dtype: str = "c128", *, dx=1.0, dy=1.0,
+                 mass=1.0, hbar=1.0, bc="periodic", device="cuda"):
+        self.problem = tsq_problem(int(nx), int(ny), float(dx), float(dy), float(mass),
+                                   float(hbar), float(dt), BCS[bc], DTYPES[dtype])
+        self.dtype = dtype
+        self.handle = tsq_plan_create(self.problem)
+        self.device = device
+        self._ws = None
+        self._V = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                tsq_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return tsq_workspace_size(self.handle)
+
+    def set_schedule(self, steps_per_pass: int = 0, segment_rows: int = 0,
+                     pairs_per_lane: int = 0) -> None:
+        tsq_plan_set_schedule(self.handle, steps_per_pass, segment_rows, pairs_per_lane)
+
+    def schedule(self) -> Tuple[int, int, int]:
+        return tsq_plan_get_schedule(self.handle)
+
+    def workspace(self):
+        torch = _torch()
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def set_potential(self, V) -> None:
+        torch = _torch()
+        if V.dtype != torch.float64 or not V.is_contiguous() or tuple(V.shape) != (self.problem.ny, self.problem.nx):
+            raise ValueError("V must be a contiguous float64 (ny, nx) device tensor")
+        ws = self.workspace()
+        tsq_set_potential(self.handle, V.data_ptr(), ws.data_ptr(), ws.numel(),
+                          _stream_handle(V.device))
+        self._V = V
+
+    def _check_psi(self, psi) -> None:
+        torch = _torch()
+        want = torch.complex128 if self.dtype == "c128" else torch.complex64
+        if psi.dtype != want or not psi.is_contiguous() or tuple(psi.shape) != (self.problem.ny, self.problem.nx):
+            raise ValueError(f"psi must be a contiguous {want} (ny, nx) device tensor")
+
+    def evolve(self, psi, steps: int):
+        """Apply U2(dt)^steps to psi in place and return it."""
+        self._check_psi(psi)
+        ws = self.workspace()
+        tsq_evolve(self.handle, psi.data_ptr(), steps, ws.data_ptr(), ws.numel(),
+                   _stream_handle(psi.device))
+        return psi
+
+    def observables(self, psi, V=None) -> Tuple[float, float]:
+        """(norm, energy) of psi in FP64; synchronises the current stream."""
+        self._check_psi(psi)
+        V = self._V if V is None else V
+        if V is None:
+            raise ValueError("no potential given")
+        ws = self.workspace()
+        return tsq_observables(self.handle, psi.data_ptr(), V.data_ptr(), ws.data_ptr(),
+                               ws.numel(), _stream_handle(psi.device))
+
+
+def _dtype_name(t) -> str:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return "c128"
+    if t.dtype == torch.complex64:
+        return "c64"
+    raise ValueError(f"psi dtype {t.dtype} is not complex64/complex128")
+
+
+def evolve(psi, V, dt: float, steps: int, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
+           bc="periodic", steps_per_pass: int = 0, segment_rows: int = 0,
+           pairs_per_lane: int = 0):
+    """Evolve the device tensor psi (ny, nx) in place by `steps` second-order steps."""
+    ny, nx = psi.shape
+    plan = Plan(nx, ny, dt, _dtype_name(psi), dx=dx, dy=dy, mass=mass, hbar=hbar, bc=bc,
+                device=psi.device)
+    plan.set_schedule(steps_per_pass, segment_rows, pairs_per_lane)
+    plan.set_potential(V)
+    plan.evolve(psi, steps)
+    return psi
+
+
+def observables(psi, V, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0, bc="periodic") -> Tuple[float, float]:
+    ny, nx = psi.shape
+    plan = Plan(nx, ny, 0.0, _dtype_name(psi), dx=dx, dy=dy, mass=mass, hbar=hbar, bc=bc,
+                device=psi.device)
+    return plan.observables(psi, V)

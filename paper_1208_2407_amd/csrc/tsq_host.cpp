@@ -1,0 +1,292 @@
+// C ABI of the second-order Trotter-Suzuki solver: validation, FP64
+// coefficients, workspace layout, the pass schedule and kernel launches.
+// The operations and their citations are documented in include/tsq.h.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tsq.h"
+#include "tsq_internal.h"
+
+struct tsq_plan {
+    tsq_problem p;
+    double Jx, Jy, eps0;
+    tsq::Coef64 oxh, oyh, ox2, oy2;
+    int steps_per_pass;   // 0 = default
+    int seg_rows;         // 0 = default
+    int ppl;              // 0 = default
+    size_t sites, elem, pelem;
+    size_t off_psi2, off_ptab, off_scratch, ws_bytes;
+    const void* ws_bound;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return TSQ_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Block exponential of hopping energy J acting for tau: s = sin al,
+// d = 1 - cos al = 2 sin^2(al/2), al = tau J / hbar.
+tsq::Coef64 block_coef(double tau, double J, double hbar) {
+    const double al = tau * J / hbar;
+    const double h = std::sin(0.5 * al);
+    return tsq::Coef64{std::sin(al), 2.0 * h * h};
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+constexpr size_t kScratchBytes = (2 * tsq::kReduceBlocks + 2) * sizeof(double);
+
+// Default schedule: steps per pass and the wavefront segment height that
+// gives at least ~16 wavefronts per compute unit on 256 CUs.
+int default_steps_per_pass(const tsq_plan* p) {
+    (void)p;
+    return 1;
+}
+
+int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl) {
+    const tsq::MarchGeometry g = tsq::march_geometry(p->p.nx, p->p.ny, steps, last, ppl, 2);
+    const long long target_tiles = 4096;
+    long long segs = (target_tiles + g.nstrips - 1) / g.nstrips;
+    const long long pairs = p->p.ny / 2;
+    if (segs > pairs) segs = pairs;
+    if (segs < 1) segs = 1;
+    long long pairs_per_seg = (pairs + segs - 1) / segs;
+    const long long min_pairs = 8;
+    if (pairs_per_seg < min_pairs) pairs_per_seg = min_pairs;
+    return (int)(2 * pairs_per_seg);
+}
+
+int pairs_per_lane(const tsq_plan* p) {
+    if (p->ppl) return p->ppl;
+    return p->p.dtype == TSQ_C64 ? 2 : 1;
+}
+
+int check_ws(const tsq_plan* plan, const void* ws, size_t ws_bytes) {
+    if (ws == nullptr) return fail(TSQ_ERR_ARG, "workspace pointer is null");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(TSQ_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < plan->ws_bytes)
+        return fail(TSQ_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                    ws_bytes, plan->ws_bytes);
+    return TSQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsq_abi_version(void) { return TSQ_ABI_VERSION; }
+
+const char* tsq_last_error(void) { return g_err.c_str(); }
+
+int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
+    if (pr == nullptr || out == nullptr) return fail(TSQ_ERR_ARG, "null problem or output pointer");
+    if (pr->nx < 2 || pr->ny < 2)
+        return fail(TSQ_ERR_SHAPE, "mesh %d x %d: each side must be >= 2", pr->nx, pr->ny);
+    if (pr->bc != TSQ_BC_PERIODIC && pr->bc != TSQ_BC_CLOSED)
+        return fail(TSQ_ERR_ARG, "unknown boundary condition %d", pr->bc);
+    if (pr->bc == TSQ_BC_PERIODIC && ((pr->nx & 1) || (pr->ny & 1)))
+        return fail(TSQ_ERR_SHAPE,
+                    "mesh %d x %d: periodic boundaries need even sides (pairs must tile each line)",
+                    pr->nx, pr->ny);
+    if ((long long)pr->nx * (long long)pr->ny > 0x7fffffffLL)
+        return fail(TSQ_ERR_SHAPE, "mesh %d x %d exceeds 2^31-1 sites", pr->nx, pr->ny);
+    if (!finite_pos(pr->dx) || !finite_pos(pr->dy))
+        return fail(TSQ_ERR_ARG, "spacings must be finite and > 0 (dx=%g, dy=%g)", pr->dx, pr->dy);
+    if (!finite_pos(pr->mass)) return fail(TSQ_ERR_ARG, "mass must be finite and > 0 (%g)", pr->mass);
+    if (!finite_pos(pr->hbar)) return fail(TSQ_ERR_ARG, "hbar must be finite and > 0 (%g)", pr->hbar);
+    if (!std::isfinite(pr->dt)) return fail(TSQ_ERR_ARG, "dt must be finite (%g)", pr->dt);
+    if (pr->dtype != TSQ_C64 && pr->dtype != TSQ_C128)
+        return fail(TSQ_ERR_DTYPE, "unknown dtype %d", pr->dtype);
+    if (pr->bc == TSQ_BC_CLOSED)
+        return fail(TSQ_ERR_UNSUPPORTED, "closed boundaries are not implemented in this build");
+
+    tsq_plan* p = new (std::nothrow) tsq_plan();
+    if (!p) return fail(TSQ_ERR_ARG, "out of host memory");
+    p->p = *pr;
+    const double hb = pr->hbar, m = pr->mass;
+    p->Jx = hb * hb / (2.0 * m * pr->dx * pr->dx);
+    p->Jy = hb * hb / (2.0 * m * pr->dy * pr->dy);
+    p->eps0 = hb * hb / (m * pr->dx * pr->dx) + hb * hb / (m * pr->dy * pr->dy);
+    const double h = 0.5 * pr->dt;
+    p->oxh = block_coef(h, p->Jx, hb);
+    p->oyh = block_coef(h, p->Jy, hb);
+    p->ox2 = block_coef(pr->dt, p->Jx, hb);
+    p->oy2 = block_coef(pr->dt, p->Jy, hb);
+    p->steps_per_pass = 0;
+    p->seg_rows = 0;
+    p->ppl = 0;
+    p->sites = (size_t)pr->nx * (size_t)pr->ny;
+    p->elem = pr->dtype == TSQ_C128 ? 16 : 8;
+    p->pelem = 16;  // complex128: exp(-i phi); complex64: hi + lo complex floats
+    p->off_psi2 = 0;
+    p->off_ptab = align_up(p->sites * p->elem, 256);
+    p->off_scratch = align_up(p->off_ptab + p->sites * p->pelem, 256);
+    p->ws_bytes = p->off_scratch + kScratchBytes;
+    p->ws_bound = nullptr;
+    *out = p;
+    return ok();
+}
+
+int tsq_plan_destroy(tsq_plan* plan) {
+    delete plan;
+    return ok();
+}
+
+int tsq_workspace_size(const tsq_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(TSQ_ERR_ARG, "null plan or output pointer");
+    *bytes = plan->ws_bytes;
+    return ok();
+}
+
+int tsq_plan_set_schedule(tsq_plan* plan, int32_t steps_per_pass, int32_t segment_rows,
+                          int32_t pairs_per_lane_) {
+    if (!plan) return fail(TSQ_ERR_ARG, "null plan");
+    if (pairs_per_lane_ < 0 || pairs_per_lane_ > 2)
+        return fail(TSQ_ERR_ARG, "pairs_per_lane %d outside 0..2", pairs_per_lane_);
+    if (steps_per_pass < 0 || steps_per_pass > tsq::kMaxSteps)
+        return fail(TSQ_ERR_ARG, "steps_per_pass %d outside 0..%d", steps_per_pass, tsq::kMaxSteps);
+    if (segment_rows < 0 || (segment_rows & 1))
+        return fail(TSQ_ERR_ARG, "segment_rows %d must be even and >= 0", segment_rows);
+    plan->steps_per_pass = steps_per_pass;
+    plan->seg_rows = segment_rows;
+    plan->ppl = pairs_per_lane_;
+    return ok();
+}
+
+int tsq_plan_get_schedule(const tsq_plan* plan, int32_t* steps_per_pass, int32_t* segment_rows,
+                          int32_t* pairs_per_lane_) {
+    if (!plan || !steps_per_pass || !segment_rows || !pairs_per_lane_)
+        return fail(TSQ_ERR_ARG, "null argument");
+    *steps_per_pass = plan->steps_per_pass ? plan->steps_per_pass : default_steps_per_pass(plan);
+    *segment_rows = plan->seg_rows;
+    *pairs_per_lane_ = pairs_per_lane(plan);
+    return ok();
+}
+
+int tsq_set_potential(tsq_plan* plan, const double* V, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !V) return fail(TSQ_ERR_ARG, "null plan or potential");
+    int rc = check_ws(plan, ws, ws_bytes);
+    if (rc) return rc;
+    char* w = static_cast<char*>(ws);
+    hipError_t e = tsq::launch_phase_table(plan->p.dtype, V, w + plan->off_ptab,
+                                           (long long)plan->sites, plan->p.dt, plan->eps0,
+                                           plan->p.hbar, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "phase table launch: %s", hipGetErrorString(e));
+    plan->ws_bound = ws;
+    return ok();
+}
+
+int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !psi) return fail(TSQ_ERR_ARG, "null plan or psi");
+    if (steps < 0) return fail(TSQ_ERR_ARG, "steps must be >= 0 (%lld)", (long long)steps);
+    if (reinterpret_cast<uintptr_t>(psi) % 16 != 0) return fail(TSQ_ERR_ARG, "psi must be 16-byte aligned");
+    int rc = check_ws(plan, ws, ws_bytes);
+    if (rc) return rc;
+    if (plan->ws_bound == nullptr) return fail(TSQ_ERR_STATE, "tsq_set_potential has not been called");
+    if (plan->ws_bound != ws)
+        return fail(TSQ_ERR_STATE, "workspace differs from the one given to tsq_set_potential");
+    if (steps == 0) return ok();
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    void* buf[2] = {psi, w + plan->off_psi2};
+    const int S = plan->steps_per_pass ? plan->steps_per_pass : default_steps_per_pass(plan);
+    const int ppl = pairs_per_lane(plan);
+
+    // Pass sizes: S steps each, the remainder in the last pass; an odd pass
+    // count leaves the result in the second buffer, so split one pass if any
+    // holds more than one step, else copy back at the end.
+    std::vector<int> sizes;
+    for (int64_t done = 0; done < steps;) {
+        int64_t n = steps - done < S ? steps - done : S;
+        sizes.push_back((int)n);
+        done += n;
+    }
+    bool copy_back = false;
+    if (sizes.size() & 1) {
+        size_t j = sizes.size();
+        for (size_t i = sizes.size(); i-- > 0;)
+            if (sizes[i] >= 2) { j = i; break; }
+        if (j < sizes.size()) {
+            int a = sizes[j] / 2, b = sizes[j] - a;
+            sizes[j] = a;
+            sizes.insert(sizes.begin() + j + 1, b);
+        } else {
+            copy_back = true;
+        }
+    }
+
+    tsq::PassDesc d;
+    d.ptab = w + plan->off_ptab;
+    d.nx = plan->p.nx;
+    d.ny = plan->p.ny;
+    d.pairs_per_lane = ppl;
+    d.oxh = plan->oxh;
+    d.oyh = plan->oyh;
+    d.ox2 = plan->ox2;
+    d.oy2 = plan->oy2;
+    for (size_t i = 0; i < sizes.size(); ++i) {
+        d.src = buf[i & 1];
+        d.dst = buf[(i + 1) & 1];
+        d.steps = sizes[i];
+        d.first = (i == 0);
+        d.last = (i + 1 == sizes.size());
+        d.seg_rows = plan->seg_rows ? plan->seg_rows : default_seg_rows(plan, d.steps, d.last, ppl);
+        hipError_t e = tsq::launch_pass(plan->p.dtype, d, s);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "step pass launch: %s", hipGetErrorString(e));
+    }
+    if (copy_back) {
+        hipError_t e = hipMemcpyAsync(psi, buf[1], plan->sites * plan->elem, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "copy back: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
+
+int tsq_observables(const tsq_plan* plan, const void* psi, const double* V, double* norm_out,
+                    double* energy_out, void* ws, size_t ws_bytes, void* stream) {
+    if (!plan || !psi || !V || !norm_out || !energy_out) return fail(TSQ_ERR_ARG, "null argument");
+    int rc = check_ws(plan, ws, ws_bytes);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* scratch = reinterpret_cast<double*>(static_cast<char*>(ws) + plan->off_scratch);
+    double* result = scratch + 2 * tsq::kReduceBlocks;
+    const int nblocks = plan->p.ny < tsq::kReduceBlocks ? plan->p.ny : tsq::kReduceBlocks;
+    hipError_t e = tsq::launch_observables(plan->p.dtype, psi, V, plan->p.nx, plan->p.ny, plan->Jx,
+                                           plan->Jy, plan->eps0, scratch, nblocks, result, s);
+    if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "observables launch: %s", hipGetErrorString(e));
+    double host[2];
+    e = hipMemcpyAsync(host, result, sizeof host, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "observables: %s", hipGetErrorString(e));
+    *norm_out = host[0];
+    *energy_out = host[1];
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+"""Host-side contract of the C ABI: the library loads, exports what include/tsq.h
+declares, and validates problems before touching a device (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_1208_2407_amd as tsq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def setup_module(_):
+    if not os.path.exists(tsq.LIB_PATH):
+        from paper_1208_2407_amd import build
+        build.build()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "tsq.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(tsq_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(tsq.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(tsq.EXPORTED)
+
+
+def test_abi_version():
+    assert tsq.tsq_abi_version() == 1
+
+
+def problem(**kw):
+    base = dict(nx=64, ny=32, dx=1.0, dy=1.0, mass=1.0, hbar=1.0, dt=0.1, bc=0, dtype=1)
+    base.update(kw)
+    return tsq.tsq_problem(*[base[k] for k, _ in tsq.tsq_problem._fields_])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nx=1), -2), (dict(ny=0), -2), (dict(nx=63), -2), (dict(ny=33), -2),
+    (dict(nx=65536, ny=65536), -2),
+    (dict(dx=0.0), -1), (dict(dy=-1.0), -1), (dict(mass=math.nan), -1), (dict(hbar=math.inf), -1),
+    (dict(dt=math.nan), -1), (dict(dt=math.inf), -1),
+    (dict(dtype=7), -3), (dict(bc=5), -1), (dict(bc=1), -7),
+])
+def test_plan_create_rejects(kw, status):
+    with pytest.raises(tsq.TsqError) as ei:
+        tsq.tsq_plan_create(problem(**kw))
+    assert ei.value.status == status
+    assert tsq.tsq_last_error() != ""
+
+
+def test_plan_create_accepts_negative_dt_and_reports_workspace():
+    for dtype, elem in ((1, 16), (0, 8)):
+        h = tsq.tsq_plan_create(problem(dt=-0.3, dtype=dtype))
+        try:
+            n = tsq.tsq_workspace_size(h)
+            sites = 64 * 32
+            assert n >= sites * elem + sites * 16
+            assert tsq.tsq_last_error() == ""
+        finally:
+            tsq.tsq_plan_destroy(h)
+
+
+def test_schedule_validation():
+    h = tsq.tsq_plan_create(problem())
+    try:
+        tsq.tsq_plan_set_schedule(h, 3, 64, 2)
+        assert tsq.tsq_plan_get_schedule(h) == (3, 64, 2)
+        tsq.tsq_plan_set_schedule(h, 0, 0, 0)
+        assert tsq.tsq_plan_get_schedule(h)[2] in (1, 2)
+        for bad in ((-1, 0, 0), (9, 0, 0), (2, 7, 0), (2, -2, 0), (1, 0, 3)):
+            with pytest.raises(tsq.TsqError) as ei:
+                tsq.tsq_plan_set_schedule(h, *bad)
+            assert ei.value.status == -1
+    finally:
+        tsq.tsq_plan_destroy(h)
+
+
+def test_calls_reject_null_and_out_of_order_before_any_launch():
+    lib = tsq.load_library()
+    h = tsq.tsq_plan_create(problem())
+    try:
+        # null pointers and misuse are refused on the host, so these never reach HIP
+        assert lib.tsq_evolve(h, None, 1, None, 0, None) == -1
+        assert lib.tsq_evolve(h, 16, -1, 256, 1 << 30, None) == -1
+        assert lib.tsq_evolve(h, 16, 1, 256, 16, None) == -4          # workspace too small
+        assert lib.tsq_evolve(h, 16, 1, 256 + 8, 1 << 30, None) == -4  # misaligned workspace
+        assert lib.tsq_evolve(h, 16, 1, 256, 1 << 30, None) == -6      # no potential set
+        assert lib.tsq_evolve(h, 8, 1, 256, 1 << 30, None) == -1       # misaligned psi
+        assert lib.tsq_set_potential(h, None, 256, 1 << 30, None) == -1
+        assert lib.tsq_set_potential(h, 16, 256, 16, None) == -4
+        n, e = ctypes.c_double(), ctypes.c_double()
+        assert lib.tsq_observables(h, None, 16, ctypes.byref(n), ctypes.byref(e), 256, 1 << 30, None) == -1
+        assert lib.tsq_workspace_size(None, None) == -1
+        assert lib.tsq_plan_destroy(None) == 0
+    finally:
+        tsq.tsq_plan_destroy(h)
