@@ -121,6 +121,11 @@ int tsq_plan_set_schedule(tsq_plan* plan, int32_t steps_per_pass, int32_t segmen
 int tsq_plan_get_schedule(const tsq_plan* plan, int32_t* steps_per_pass, int32_t* segment_rows,
                           int32_t* pairs_per_lane);
 
+/* Number of kernel launches (fused passes) tsq_evolve makes for `steps`
+ * under the plan's schedule, and whether it ends with a device-to-device copy
+ * (odd pass count that cannot be split).  Host only.  Errors: TSQ_ERR_ARG. */
+int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int32_t* copy_back);
+
 /* Row a0: build the phase table exp(-i dt (V_l + eps0) / hbar) in FP64 from
  * the device array V_dev (nx*ny doubles) into the workspace `ws` of
  * `ws_bytes` bytes (device, 256-byte aligned), rounded to the plan's dtype.

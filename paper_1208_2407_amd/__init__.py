@@ -29,7 +29,7 @@ BCS = {"periodic": 0, "closed": 1}
 
 EXPORTED = ("tsq_abi_version", "tsq_last_error", "tsq_plan_create", "tsq_plan_destroy",
             "tsq_workspace_size", "tsq_plan_set_schedule", "tsq_plan_get_schedule",
-            "tsq_set_potential", "tsq_evolve", "tsq_observables")
+            "tsq_evolve_passes", "tsq_set_potential", "tsq_evolve", "tsq_observables")
 
 
 class TsqError(RuntimeError):
@@ -68,6 +68,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.tsq_plan_set_schedule.argtypes = [vp, i32, i32, i32]
     lib.tsq_plan_get_schedule.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                           ctypes.POINTER(i32)]
+    lib.tsq_evolve_passes.argtypes = [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.tsq_set_potential.argtypes = [vp, vp, vp, sz, vp]
     lib.tsq_evolve.argtypes = [vp, vp, i64, vp, sz, vp]
     lib.tsq_observables.argtypes = [vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d), vp, sz, vp]
@@ -120,6 +121,12 @@ def tsq_plan_get_schedule(plan: int) -> Tuple[int, int, int]:
     _check(load_library().tsq_plan_get_schedule(plan, ctypes.byref(s), ctypes.byref(r),
                                                 ctypes.byref(p)))
     return s.value, r.value, p.value
+
+
+def tsq_evolve_passes(plan: int, steps: int) -> Tuple[int, bool]:
+    n, c = ctypes.c_int64(), ctypes.c_int32()
+    _check(load_library().tsq_evolve_passes(plan, int(steps), ctypes.byref(n), ctypes.byref(c)))
+    return n.value, bool(c.value)
 
 
 def tsq_set_potential(plan: int, V_dev: int, ws: int, ws_bytes: int, stream: int) -> None:
@@ -187,6 +194,10 @@ class Plan:
 
     def schedule(self) -> Tuple[int, int, int]:
         return tsq_plan_get_schedule(self.handle)
+
+    def passes(self, steps: int) -> Tuple[int, bool]:
+        """(kernel launches, trailing copy) that evolve(psi, steps) makes."""
+        return tsq_evolve_passes(self.handle, steps)
 
     def workspace(self):
         torch = _torch()

@@ -1,0 +1,98 @@
+"""Schedule autotuner for the fused step kernel.
+
+A schedule is (steps_per_pass, segment_rows, pairs_per_lane) of
+``tsq_plan_set_schedule``.  Every schedule gives bitwise identical results, so
+the tuner only times: it evolves a scratch copy of the state for a few passes
+under each candidate (HIP events on the current stream), keeps the fastest,
+and caches the choice per (device architecture, dtype, mesh) in a JSON file
+(``$TSQ_AUTOTUNE_CACHE``, default ``~/.cache/tsq/autotune.json``).
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, List, Optional, Tuple
+
+Schedule = Tuple[int, int, int]
+
+DEFAULT_CANDIDATES: List[Schedule] = [
+    (S, seg, ppl) for S in (1, 2, 3, 4) for ppl in (1, 2) for seg in (0, 32, 64, 128)
+]
+
+
+def cache_path() -> str:
+    return os.environ.get("TSQ_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "tsq", "autotune.json"))
+
+
+def _key(arch: str, dtype: str, nx: int, ny: int) -> str:
+    return f"{arch}|{dtype}|{nx}x{ny}"
+
+
+def _load() -> Dict[str, dict]:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db: Dict[str, dict]) -> None:
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass
+
+
+def time_schedule(plan, psi, schedule: Schedule, steps: int, repeats: int = 2) -> float:
+    """Best-of-`repeats` milliseconds of plan.evolve(psi, steps) under `schedule`."""
+    import torch
+    plan.set_schedule(*schedule)
+    plan.evolve(psi, min(steps, 2 * schedule[0]))  # warm the code path
+    best = float("inf")
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.evolve(psi, steps)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: int = 48,
+         use_cache: bool = True, log=None) -> Tuple[Schedule, Dict[str, float]]:
+    """Pick the fastest schedule for this plan's mesh and dtype; set it on the plan.
+
+    `psi` is not modified (a scratch copy is evolved).  Returns the schedule and
+    the timing table {"S,seg,ppl": ms}."""
+    import torch
+    arch = torch.cuda.get_device_properties(psi.device).gcnArchName.split(":")[0]
+    key = _key(arch, plan.dtype, plan.problem.nx, plan.problem.ny)
+    db = _load() if use_cache else {}
+    if use_cache and key in db:
+        sched = tuple(db[key]["schedule"])
+        plan.set_schedule(*sched)
+        return sched, db[key].get("table", {})
+    scratch = psi.clone()
+    table: Dict[str, float] = {}
+    best: Optional[Schedule] = None
+    for cand in (candidates or DEFAULT_CANDIDATES):
+        ms = time_schedule(plan, scratch, cand, steps)
+        table[",".join(map(str, cand))] = ms
+        if log:
+            log(f"autotune {key} S={cand[0]} seg={cand[1]} ppl={cand[2]}: {ms:.3f} ms")
+        if best is None or ms < table[",".join(map(str, best))]:
+            best = cand
+    del scratch
+    plan.set_schedule(*best)
+    if use_cache:
+        db[key] = {"schedule": list(best), "table": table, "steps": steps}
+        _store(db)
+    return best, table

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -61,24 +62,99 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 constexpr size_t kScratchBytes = (2 * tsq::kReduceBlocks + 2) * sizeof(double);
 
-// Default schedule: steps per pass and the wavefront segment height that
-// gives at least ~16 wavefronts per compute unit on 256 CUs.
+// Default schedule.  Steps per pass: 4 (the deepest fusion built).  Segment
+// height: as many wavefront tiles as the device holds resident at once (one
+// round, no tail of a partly filled second round), each segment at least 2K
+// row pairs long so the discarded warm-up pairs stay below half the work.
 int default_steps_per_pass(const tsq_plan* p) {
     (void)p;
-    return 1;
+    return tsq::kMaxSteps;
+}
+
+struct DeviceShape {
+    int device = -1;
+    int cus = 0;
+};
+thread_local DeviceShape g_dev;
+
+int device_cus() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (g_dev.device != dev) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+        g_dev.device = dev;
+        g_dev.cus = cus;
+    }
+    return g_dev.cus;
+}
+
+int occupancy_cached(int dtype, int steps, bool last, int ppl) {
+    // [dtype][steps][last][ppl]; 0 = not yet queried
+    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3];
+    std::atomic<int>& slot = table[dtype & 1][steps][last ? 1 : 0][ppl];
+    int v = slot.load(std::memory_order_relaxed);
+    if (v == 0) {
+        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl);
+        if (v <= 0) v = 1;
+        slot.store(v, std::memory_order_relaxed);
+    }
+    return v;
 }
 
 int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl) {
     const tsq::MarchGeometry g = tsq::march_geometry(p->p.nx, p->p.ny, steps, last, ppl, 2);
-    const long long target_tiles = 4096;
-    long long segs = (target_tiles + g.nstrips - 1) / g.nstrips;
+    int cus = device_cus();
+    if (cus <= 0) cus = 256;
+    const long long slots =
+        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl) * tsq::kWavesPerBlock;
     const long long pairs = p->p.ny / 2;
-    if (segs > pairs) segs = pairs;
+    long long segs = slots / g.nstrips;
     if (segs < 1) segs = 1;
+    if (segs > pairs) segs = pairs;
     long long pairs_per_seg = (pairs + segs - 1) / segs;
-    const long long min_pairs = 8;
+    const long long min_pairs = 2LL * (steps + (last ? 1 : 0));
     if (pairs_per_seg < min_pairs) pairs_per_seg = min_pairs;
     return (int)(2 * pairs_per_seg);
+}
+
+// Pass sizes as runs of (steps per pass, repeat): S steps each, the remainder
+// in the last pass.  An odd pass count would leave the result in the second
+// buffer, so the last pass holding more than one step is split in two; if no
+// pass can be split the caller copies the result back.
+struct Run {
+    int size;
+    int64_t count;
+};
+
+bool pass_runs(int64_t steps, int S, std::vector<Run>& runs) {
+    runs.clear();
+    const int64_t full = steps / S;
+    const int rem = (int)(steps % S);
+    if (full > 0) runs.push_back(Run{S, full});
+    if (rem > 0) runs.push_back(Run{rem, 1});
+    const int64_t total = full + (rem > 0 ? 1 : 0);
+    if (!(total & 1)) return false;
+    for (size_t i = runs.size(); i-- > 0;) {
+        if (runs[i].size < 2) continue;
+        const Run r = runs[i];
+        const int a = r.size / 2, b = r.size - a;
+        std::vector<Run> tail(runs.begin() + i + 1, runs.end());
+        runs.resize(i);
+        if (r.count > 1) runs.push_back(Run{r.size, r.count - 1});
+        runs.push_back(Run{a, 1});
+        runs.push_back(Run{b, 1});
+        runs.insert(runs.end(), tail.begin(), tail.end());
+        return false;
+    }
+    return true;
+}
+
+int64_t run_passes(const std::vector<Run>& runs) {
+    int64_t n = 0;
+    for (const Run& r : runs) n += r.count;
+    return n;
 }
 
 int pairs_per_lane(const tsq_plan* p) {
@@ -189,6 +265,17 @@ int tsq_plan_get_schedule(const tsq_plan* plan, int32_t* steps_per_pass, int32_t
     return ok();
 }
 
+int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int32_t* copy_back) {
+    if (!plan || !passes || !copy_back) return fail(TSQ_ERR_ARG, "null argument");
+    if (steps < 0) return fail(TSQ_ERR_ARG, "steps must be >= 0 (%lld)", (long long)steps);
+    std::vector<Run> runs;
+    const int S = plan->steps_per_pass ? plan->steps_per_pass : default_steps_per_pass(plan);
+    const bool cb = steps > 0 && pass_runs(steps, S, runs);
+    *passes = run_passes(runs);
+    *copy_back = cb ? 1 : 0;
+    return ok();
+}
+
 int tsq_set_potential(tsq_plan* plan, const double* V, void* ws, size_t ws_bytes, void* stream) {
     if (!plan || !V) return fail(TSQ_ERR_ARG, "null plan or potential");
     int rc = check_ws(plan, ws, ws_bytes);
@@ -219,28 +306,9 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
     const int S = plan->steps_per_pass ? plan->steps_per_pass : default_steps_per_pass(plan);
     const int ppl = pairs_per_lane(plan);
 
-    // Pass sizes: S steps each, the remainder in the last pass; an odd pass
-    // count leaves the result in the second buffer, so split one pass if any
-    // holds more than one step, else copy back at the end.
-    std::vector<int> sizes;
-    for (int64_t done = 0; done < steps;) {
-        int64_t n = steps - done < S ? steps - done : S;
-        sizes.push_back((int)n);
-        done += n;
-    }
-    bool copy_back = false;
-    if (sizes.size() & 1) {
-        size_t j = sizes.size();
-        for (size_t i = sizes.size(); i-- > 0;)
-            if (sizes[i] >= 2) { j = i; break; }
-        if (j < sizes.size()) {
-            int a = sizes[j] / 2, b = sizes[j] - a;
-            sizes[j] = a;
-            sizes.insert(sizes.begin() + j + 1, b);
-        } else {
-            copy_back = true;
-        }
-    }
+    std::vector<Run> runs;
+    const bool copy_back = pass_runs(steps, S, runs);
+    const int64_t npasses = run_passes(runs);
 
     tsq::PassDesc d;
     d.ptab = w + plan->off_ptab;
@@ -251,15 +319,20 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
     d.oyh = plan->oyh;
     d.ox2 = plan->ox2;
     d.oy2 = plan->oy2;
-    for (size_t i = 0; i < sizes.size(); ++i) {
-        d.src = buf[i & 1];
-        d.dst = buf[(i + 1) & 1];
-        d.steps = sizes[i];
-        d.first = (i == 0);
-        d.last = (i + 1 == sizes.size());
-        d.seg_rows = plan->seg_rows ? plan->seg_rows : default_seg_rows(plan, d.steps, d.last, ppl);
-        hipError_t e = tsq::launch_pass(plan->p.dtype, d, s);
-        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "step pass launch: %s", hipGetErrorString(e));
+    int64_t i = 0;
+    for (const Run& r : runs) {
+        for (int64_t k = 0; k < r.count; ++k, ++i) {
+            d.src = buf[i & 1];
+            d.dst = buf[(i + 1) & 1];
+            d.steps = r.size;
+            d.first = (i == 0);
+            d.last = (i + 1 == npasses);
+            d.seg_rows = plan->seg_rows ? plan->seg_rows
+                                        : default_seg_rows(plan, d.steps, d.last, ppl);
+            hipError_t e = tsq::launch_pass(plan->p.dtype, d, s);
+            if (e != hipSuccess)
+                return fail(TSQ_ERR_DEVICE, "step pass launch: %s", hipGetErrorString(e));
+        }
     }
     if (copy_back) {
         hipError_t e = hipMemcpyAsync(psi, buf[1], plan->sites * plan->elem, hipMemcpyDeviceToDevice, s);

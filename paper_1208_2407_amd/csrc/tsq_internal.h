@@ -43,6 +43,10 @@ struct MarchGeometry {
 MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per_lane,
                              int seg_rows);
 
+// Resident blocks per compute unit of one march kernel instance (0 if the
+// query fails); used to size segments so a pass is one round of resident waves.
+int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane);
+
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long sites,
                               double dt, double eps0, double hbar, hipStream_t s);

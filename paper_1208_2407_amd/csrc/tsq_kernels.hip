@@ -234,80 +234,90 @@ march_kernel(const MarchArgs<typename T::R> a) {
         }
     }
 
+    // Phase factors ride in a register ring of NP slots: the pair a stage
+    // completes was loaded (with its psi) one iteration before it entered the
+    // pipeline, so the S stages use S slots, one slot waits and one is in
+    // flight.  The march loop is unrolled by NP so every slot index is static.
+    constexpr int NP = S + 2;
+    PT pr[NP][2][SPL];
     Row<R, SPL> nt, nbm;
-    {
-        const int r0 = wrap(2LL * (q0 - K), ny);
+
+    auto load_psi = [&](int t, Row<R, SPL>& top, Row<R, SPL>& bot) {
+        const int r0 = wrap(2LL * t, ny);
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-            load_pair(a.src, (long long)r0 * nx + col[p], nt, p);
-            load_pair(a.src, (long long)(r0 + 1) * nx + col[p], nbm, p);
+            load_pair(a.src, (long long)r0 * nx + col[p], top, p);
+            load_pair(a.src, (long long)(r0 + 1) * nx + col[p], bot, p);
         }
-    }
+    };
+    auto load_phase = [&](int t, PT (&slot)[2][SPL]) {
+        const int r0 = wrap(2LL * t, ny);
+        const PT* P0 = reinterpret_cast<const PT*>(a.ptab) + (long long)r0 * nx;
+        const PT* P1 = P0 + nx;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            slot[0][2 * p] = P0[col[p]];
+            slot[0][2 * p + 1] = P0[col[p] + 1];
+            slot[1][2 * p] = P1[col[p]];
+            slot[1][2 * p + 1] = P1[col[p] + 1];
+        }
+    };
 
-    for (int t = q0 - K; t <= tlast; ++t) {
-        Row<R, SPL> it = nt, ib = nbm;
-        if (t < tlast) {
-            const int r0 = wrap(2LL * (t + 1), ny);
+    const int tfirst = q0 - K;
+    load_psi(tfirst, nt, nbm);
+    load_phase(tfirst, pr[0]);
+
+    for (int tb = tfirst; tb <= tlast; tb += NP) {
 #pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-                load_pair(a.src, (long long)r0 * nx + col[p], nt, p);
-                load_pair(a.src, (long long)(r0 + 1) * nx + col[p], nbm, p);
+        for (int u = 0; u < NP; ++u) {
+            const int t = tb + u;
+            if (t > tlast) break;  // uniform per wavefront
+            Row<R, SPL> it = nt, ib = nbm;
+            if (t < tlast) {
+                load_psi(t + 1, nt, nbm);
+                load_phase(t + 1, pr[(u + 1) % NP]);
             }
-        }
-        // Phase factors of the row pair each stage completes (pair t - k).
-        PT pt[S][SPL], pb[S][SPL];
 #pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const int r0 = wrap(2LL * (t - 1 - k), ny);
-            const PT* P0 = reinterpret_cast<const PT*>(a.ptab) + (long long)r0 * nx;
-            const PT* P1 = P0 + nx;
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-                pt[k][2 * p] = P0[col[p]];
-                pt[k][2 * p + 1] = P0[col[p] + 1];
-                pb[k][2 * p] = P1[col[p]];
-                pb[k][2 * p + 1] = P1[col[p] + 1];
+            for (int k = 0; k < K; ++k) {
+                R oxs, oxd, oys, oyd;
+                if (k == 0) {
+                    oxs = a.o1xs; oxd = a.o1xd; oys = a.o1ys; oyd = a.o1yd;
+                } else if (k < S) {
+                    oxs = a.o2xs; oxd = a.o2xd; oys = a.o2ys; oyd = a.o2yd;
+                } else {
+                    oxs = a.ehxs; oxd = a.ehxd; oys = a.ehys; oyd = a.ehyd;
+                }
+                // odd factors on the boundary between pair (t-1-k) and the incoming pair
+                odd_x(hb[k], oxs, oxd);
+                odd_x(it, oxs, oxd);
+                pair_y(hb[k], it, oys, oyd);
+                if (k < S) {
+                    // even factors, phase, even factors on the completed pair t-1-k
+                    const int slot = (u - 1 - k + 2 * NP) % NP;
+                    even_x(ht[k], a.ehxs, a.ehxd);
+                    even_x(hb[k], a.ehxs, a.ehxd);
+                    pair_y(ht[k], hb[k], a.ehys, a.ehyd);
+                    phase_row(ht[k], pr[slot][0]);
+                    phase_row(hb[k], pr[slot][1]);
+                    pair_y(ht[k], hb[k], a.ehys, a.ehyd);
+                    even_x(ht[k], a.ehxs, a.ehxd);
+                    even_x(hb[k], a.ehxs, a.ehxd);
+                }
+                Row<R, SPL> ot = ht[k], ob = hb[k];
+                ht[k] = it;
+                hb[k] = ib;
+                it = ot;
+                ib = ob;
             }
-        }
+            const int qo = t - K;
+            if (qo >= q0) {
+                const long long r0 = 2LL * qo;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            R oxs, oxd, oys, oyd;
-            if (k == 0) {
-                oxs = a.o1xs; oxd = a.o1xd; oys = a.o1ys; oyd = a.o1yd;
-            } else if (k < S) {
-                oxs = a.o2xs; oxd = a.o2xd; oys = a.o2ys; oyd = a.o2yd;
-            } else {
-                oxs = a.ehxs; oxd = a.ehxd; oys = a.ehys; oyd = a.ehyd;
-            }
-            // odd factors on the boundary between pair (t-1-k) and the incoming pair
-            odd_x(hb[k], oxs, oxd);
-            odd_x(it, oxs, oxd);
-            pair_y(hb[k], it, oys, oyd);
-            if (k < S) {
-                // even factors, phase, even factors on the completed pair
-                even_x(ht[k], a.ehxs, a.ehxd);
-                even_x(hb[k], a.ehxs, a.ehxd);
-                pair_y(ht[k], hb[k], a.ehys, a.ehyd);
-                phase_row(ht[k], pt[k]);
-                phase_row(hb[k], pb[k]);
-                pair_y(ht[k], hb[k], a.ehys, a.ehyd);
-                even_x(ht[k], a.ehxs, a.ehxd);
-                even_x(hb[k], a.ehxs, a.ehxd);
-            }
-            Row<R, SPL> ot = ht[k], ob = hb[k];
-            ht[k] = it;
-            hb[k] = ib;
-            it = ot;
-            ib = ob;
-        }
-        const int qo = t - K;
-        if (qo >= q0) {
-            const long long r0 = 2LL * qo;
-#pragma unroll
-            for (int p = 0; p < PPL; ++p) {
-                if (keep[p]) {
-                    store_pair(a.dst, r0 * nx + col[p], it, p);
-                    store_pair(a.dst, (r0 + 1) * nx + col[p], ib, p);
+                for (int p = 0; p < PPL; ++p) {
+                    if (keep[p]) {
+                        store_pair(a.dst, r0 * nx + col[p], it, p);
+                        store_pair(a.dst, (r0 + 1) * nx + col[p], ib, p);
+                    }
                 }
             }
         }
@@ -442,6 +452,36 @@ MarchArgs<R> make_args(const PassDesc& d, const MarchGeometry& g) {
 }
 
 template <class T, int S, bool LAST, int PPL>
+int occupancy_march() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_kernel<T, S, LAST, PPL>,
+                                                     kWaveSize * kWavesPerBlock, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+template <class T, int S, bool LAST>
+int occupancy_ppl(int ppl) {
+    return ppl == 2 ? occupancy_march<T, S, LAST, 2>() : occupancy_march<T, S, LAST, 1>();
+}
+
+template <class T, int S>
+int occupancy_last(bool last, int ppl) {
+    return last ? occupancy_ppl<T, S, true>(ppl) : occupancy_ppl<T, S, false>(ppl);
+}
+
+template <class T>
+int occupancy_steps(int steps, bool last, int ppl) {
+    switch (steps) {
+        case 1: return occupancy_last<T, 1>(last, ppl);
+        case 2: return occupancy_last<T, 2>(last, ppl);
+        case 3: return occupancy_last<T, 3>(last, ppl);
+        case 4: return occupancy_last<T, 4>(last, ppl);
+        default: return 0;
+    }
+}
+
+template <class T, int S, bool LAST, int PPL>
 hipError_t launch_march(const PassDesc& d, hipStream_t s) {
     const MarchGeometry g = march_geometry(d.nx, d.ny, S, LAST, PPL, d.seg_rows);
     const MarchArgs<typename T::R> a = make_args<typename T::R>(d, g);
@@ -499,6 +539,11 @@ hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long 
         hipLaunchKernelGGL(phase_table_c64, dim3(blocks), dim3(threads), 0, s, V,
                            reinterpret_cast<float4*>(ptab), sites, dt, eps0, hbar);
     return hipGetLastError();
+}
+
+int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane) {
+    return dtype == 1 ? occupancy_steps<C128>(steps, last, pairs_per_lane)
+                      : occupancy_steps<C64>(steps, last, pairs_per_lane);
 }
 
 hipError_t launch_pass(int dtype, const PassDesc& d, hipStream_t s) {

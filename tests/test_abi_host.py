@@ -102,3 +102,17 @@ def test_calls_reject_null_and_out_of_order_before_any_launch():
         assert lib.tsq_plan_destroy(None) == 0
     finally:
         tsq.tsq_plan_destroy(h)
+
+
+@pytest.mark.parametrize("S,steps,passes,copy", [
+    (4, 1000, 250, False), (4, 100, 26, False), (1, 7, 7, True), (4, 1, 1, True),
+    (4, 3, 2, False), (3, 0, 0, False), (2, 5, 4, False), (1, 8, 8, False),
+    (4, 10**12 + 4, 250000000002, False),
+])
+def test_pass_count(S, steps, passes, copy):
+    h = tsq.tsq_plan_create(problem())
+    try:
+        tsq.tsq_plan_set_schedule(h, S, 0, 0)
+        assert tsq.tsq_evolve_passes(h, steps) == (passes, copy)
+    finally:
+        tsq.tsq_plan_destroy(h)
