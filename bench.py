@@ -66,7 +66,8 @@ def run_dtype(dtype: str, p, psi0, V, args):
         plan.set_schedule(*[int(v) for v in args.schedule.split(",")])
     elif not args.no_tune:
         sched, _ = autotune.tune(plan, psi, log=log if args.verbose else None)
-        log(f"{dtype}: autotuned schedule S={sched[0]} seg={sched[1]} ppl={sched[2]}")
+        log(f"{dtype}: autotuned schedule S={sched[0]} seg={sched[1]} ppl={sched[2]} "
+            f"store={sched[3]}")
     sched = plan.schedule()
     passes, copy_back = plan.passes(p.steps)
     ws = plan.workspace()
@@ -106,8 +107,9 @@ def run_dtype(dtype: str, p, psi0, V, args):
         "value": site_steps / wall,
         "ms_per_step": wall / args.steps * 1e3,
         "schedule": {"steps_per_pass": sched[0], "segment_rows": sched[1],
-                     "pairs_per_lane": sched[2], "passes_per_solve": passes,
-                     "copy_back": copy_back},
+                     "pairs_per_lane": sched[2],
+                     "phase_store": {1: "registers", 2: "lds"}[sched[3]],
+                     "passes_per_solve": passes, "copy_back": copy_back},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
@@ -116,6 +118,45 @@ def run_dtype(dtype: str, p, psi0, V, args):
         "norm_drift": norm - n_begin,
         "energy": energy,
     }
+
+
+def profile_mode(p, psi0, V, args) -> int:
+    """A short, fixed run for hardware-counter collection (no tuning, no timing loop)."""
+    import torch
+    import paper_1208_2407_amd as tsq
+
+    from paper_1208_2407_amd import autotune
+
+    if not args.schedule:
+        print("--profile-passes needs --schedule (or --schedule tuned)", file=sys.stderr)
+        return 2
+    out = {"kernel_hash": kernel_hash(), "mesh": [p.nx, p.ny], "runs": {}}
+    # reference copy of known size (1 GiB read + 1 GiB written)
+    src = torch.empty(2**27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_bytes"] = src.numel() * 8
+    for d in args.dtypes.split(","):
+        tdt = torch.complex128 if d == "c128" else torch.complex64
+        psi = psi0.to(tdt).contiguous()
+        plan = tsq.Plan(p.nx, p.ny, p.dt, d, device=psi.device)
+        plan.set_potential(V)
+        if args.schedule == "tuned":
+            autotune.tune(plan, psi)          # cached choice of an earlier bench run
+        else:
+            plan.set_schedule(*[int(v) for v in args.schedule.split(",")])
+        sched = plan.schedule()
+        steps = sched[0] * args.profile_passes
+        torch.cuda.synchronize()
+        plan.evolve(psi, steps)
+        torch.cuda.synchronize()
+        elem = 16 if d == "c128" else 8
+        out["runs"][d] = {"schedule": list(sched), "steps": steps,
+                          "passes": plan.passes(steps)[0],
+                          "algorithmic_bytes_per_launch": p.nx * p.ny * (2 * elem + 16)}
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def cpu_baseline(p, psi0_host, V_host, sample_steps: int):
@@ -136,10 +177,15 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
-    ap.add_argument("--schedule", default="", help="S,segment_rows,pairs_per_lane (skip tuning)")
+    ap.add_argument("--schedule", default="",
+                    help="S,segment_rows,pairs_per_lane,phase_store (skip tuning)")
+    ap.add_argument("--profile-passes", type=int, default=0,
+                    help="counter-collection mode: per dtype run exactly this many fused "
+                         "passes under --schedule, plus one device copy of 1 GiB (known "
+                         "bytes) to scale the HBM counters; prints a short JSON and exits")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=64)
+    ap.add_argument("--cpu-sample-steps", type=int, default=400)
     ap.add_argument("--dtypes", default="c64,c128")
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
@@ -159,6 +205,9 @@ def main() -> int:
     psi0 = wl.initial_state(p, device="cuda")
     V = wl.potential(p, device="cuda")
     torch.cuda.synchronize()
+
+    if args.profile_passes:
+        return profile_mode(p, psi0, V, args)
 
     res = {}
     for d in args.dtypes.split(","):

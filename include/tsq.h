@@ -108,18 +108,27 @@ int tsq_plan_destroy(tsq_plan* plan);
  * complex floats per site) and reduction scratch.  Host only. */
 int tsq_workspace_size(const tsq_plan* plan, size_t* bytes);
 
-/* Schedule of the fused step kernel: `steps_per_pass` time steps per read and
- * write of psi in device memory (1..4; 0 = library default), `segment_rows`
- * rows marched by one wavefront (even; 0 = default) and `pairs_per_lane`
- * x-pairs held by each lane (1 or 2; 0 = default).  Every schedule applies
- * the same operations in the same order to every site, so results are
- * bitwise identical across schedules.  get returns the values in force
- * (defaults resolved; segment_rows 0 means "sized per pass").
- * Host only.  Errors: TSQ_ERR_ARG. */
-int tsq_plan_set_schedule(tsq_plan* plan, int32_t steps_per_pass, int32_t segment_rows,
-                          int32_t pairs_per_lane);
-int tsq_plan_get_schedule(const tsq_plan* plan, int32_t* steps_per_pass, int32_t* segment_rows,
-                          int32_t* pairs_per_lane);
+/* Schedule of the fused step kernel.  Every schedule applies the same
+ * operations in the same order to every site, so results are bitwise
+ * identical across schedules; only speed changes. */
+typedef struct {
+    int32_t steps_per_pass;  /* time steps per read+write of psi in device memory:
+                                1..8, 0 = default (4) */
+    int32_t segment_rows;    /* rows marched by one wavefront: even, 0 = sized so one
+                                launch is one round of resident wavefronts */
+    int32_t pairs_per_lane;  /* x-pairs held by each lane: 1 or 2, 0 = default (1) */
+    int32_t phase_store;     /* phase factors in flight: 1 = registers (steps_per_pass
+                                <= 4), 2 = LDS (pairs_per_lane 1), 0 = default
+                                (registers up to 4 steps per pass, else LDS) */
+} tsq_schedule;
+
+/* Set the plan's schedule (host only).  Zero fields take their defaults;
+ * tsq_plan_get_schedule returns the resolved values (segment_rows stays 0 when
+ * it is sized per launch).  Errors: TSQ_ERR_ARG (null, value out of range, or
+ * an unsupported combination: registers with more than 4 steps per pass, LDS
+ * with 2 pairs per lane); the plan keeps its previous schedule. */
+int tsq_plan_set_schedule(tsq_plan* plan, const tsq_schedule* schedule);
+int tsq_plan_get_schedule(const tsq_plan* plan, tsq_schedule* schedule);
 
 /* Number of kernel launches (fused passes) tsq_evolve makes for `steps`
  * under the plan's schedule, and whether it ends with a device-to-device copy

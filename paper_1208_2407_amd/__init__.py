@@ -38,6 +38,17 @@ class TsqError(RuntimeError):
         self.status = status
 
 
+class tsq_schedule(ctypes.Structure):
+    _fields_ = [("steps_per_pass", ctypes.c_int32), ("segment_rows", ctypes.c_int32),
+                ("pairs_per_lane", ctypes.c_int32), ("phase_store", ctypes.c_int32)]
+
+    def as_tuple(self) -> Tuple[int, int, int, int]:
+        return (self.steps_per_pass, self.segment_rows, self.pairs_per_lane, self.phase_store)
+
+
+PHASE_STORE = {"default": 0, "registers": 1, "lds": 2}
+
+
 class tsq_problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
@@ -65,9 +76,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.tsq_plan_create.argtypes = [ctypes.POINTER(tsq_problem), ctypes.POINTER(vp)]
     lib.tsq_plan_destroy.argtypes = [vp]
     lib.tsq_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
-    lib.tsq_plan_set_schedule.argtypes = [vp, i32, i32, i32]
-    lib.tsq_plan_get_schedule.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                          ctypes.POINTER(i32)]
+    lib.tsq_plan_set_schedule.argtypes = [vp, ctypes.POINTER(tsq_schedule)]
+    lib.tsq_plan_get_schedule.argtypes = [vp, ctypes.POINTER(tsq_schedule)]
     lib.tsq_evolve_passes.argtypes = [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.tsq_set_potential.argtypes = [vp, vp, vp, sz, vp]
     lib.tsq_evolve.argtypes = [vp, vp, i64, vp, sz, vp]
@@ -110,17 +120,14 @@ def tsq_workspace_size(plan: int) -> int:
     return n.value
 
 
-def tsq_plan_set_schedule(plan: int, steps_per_pass: int, segment_rows: int,
-                          pairs_per_lane: int = 0) -> None:
-    _check(load_library().tsq_plan_set_schedule(plan, int(steps_per_pass), int(segment_rows),
-                                                int(pairs_per_lane)))
+def tsq_plan_set_schedule(plan: int, schedule: tsq_schedule) -> None:
+    _check(load_library().tsq_plan_set_schedule(plan, ctypes.byref(schedule)))
 
 
-def tsq_plan_get_schedule(plan: int) -> Tuple[int, int, int]:
-    s, r, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(load_library().tsq_plan_get_schedule(plan, ctypes.byref(s), ctypes.byref(r),
-                                                ctypes.byref(p)))
-    return s.value, r.value, p.value
+def tsq_plan_get_schedule(plan: int) -> tsq_schedule:
+    sc = tsq_schedule()
+    _check(load_library().tsq_plan_get_schedule(plan, ctypes.byref(sc)))
+    return sc
 
 
 def tsq_evolve_passes(plan: int, steps: int) -> Tuple[int, bool]:
@@ -189,11 +196,14 @@ class Plan:
         return tsq_workspace_size(self.handle)
 
     def set_schedule(self, steps_per_pass: int = 0, segment_rows: int = 0,
-                     pairs_per_lane: int = 0) -> None:
-        tsq_plan_set_schedule(self.handle, steps_per_pass, segment_rows, pairs_per_lane)
+                     pairs_per_lane: int = 0, phase_store: int = 0) -> None:
+        """Zero fields take the library defaults; phase_store 1 = registers, 2 = LDS."""
+        tsq_plan_set_schedule(self.handle, tsq_schedule(int(steps_per_pass), int(segment_rows),
+                                                        int(pairs_per_lane), int(phase_store)))
 
-    def schedule(self) -> Tuple[int, int, int]:
-        return tsq_plan_get_schedule(self.handle)
+    def schedule(self) -> Tuple[int, int, int, int]:
+        """(steps_per_pass, segment_rows, pairs_per_lane, phase_store) in force."""
+        return tsq_plan_get_schedule(self.handle).as_tuple()
 
     def passes(self, steps: int) -> Tuple[int, bool]:
         """(kernel launches, trailing copy) that evolve(psi, steps) makes."""
@@ -250,12 +260,12 @@ def _dtype_name(t) -> str:
 
 def evolve(psi, V, dt: float, steps: int, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
            bc="periodic", steps_per_pass: int = 0, segment_rows: int = 0,
-           pairs_per_lane: int = 0):
+           pairs_per_lane: int = 0, phase_store: int = 0):
     """Evolve the device tensor psi (ny, nx) in place by `steps` second-order steps."""
     ny, nx = psi.shape
     plan = Plan(nx, ny, dt, _dtype_name(psi), dx=dx, dy=dy, mass=mass, hbar=hbar, bc=bc,
                 device=psi.device)
-    plan.set_schedule(steps_per_pass, segment_rows, pairs_per_lane)
+    plan.set_schedule(steps_per_pass, segment_rows, pairs_per_lane, phase_store)
     plan.set_potential(V)
     plan.evolve(psi, steps)
     return psi

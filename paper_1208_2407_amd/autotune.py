@@ -1,6 +1,6 @@
 """Schedule autotuner for the fused step kernel.
 
-A schedule is (steps_per_pass, segment_rows, pairs_per_lane) of
+A schedule is (steps_per_pass, segment_rows, pairs_per_lane, phase_store) of
 ``tsq_plan_set_schedule``.  Every schedule gives bitwise identical results, so
 the tuner only times: it evolves a scratch copy of the state for a few passes
 under each candidate (HIP events on the current stream), keeps the fastest,
@@ -13,11 +13,15 @@ import json
 import os
 from typing import Dict, Iterable, List, Optional, Tuple
 
-Schedule = Tuple[int, int, int]
+Schedule = Tuple[int, int, int, int]
 
-DEFAULT_CANDIDATES: List[Schedule] = [
-    (S, seg, ppl) for S in (1, 2, 3, 4) for ppl in (1, 2) for seg in (0, 32, 64, 128)
-]
+# segment_rows 0 = one round of resident wavefronts; phase_store 1 = registers, 2 = LDS
+DEFAULT_CANDIDATES: List[Schedule] = (
+    [(S, 0, 1, store) for S in (1, 2, 3, 4) for store in (1, 2)]
+    + [(S, 0, 1, 2) for S in (5, 6, 7, 8)]
+    + [(S, 0, 2, 1) for S in (1, 2)]
+    + [(S, 96, 1, 2) for S in (4, 6)]
+)
 
 
 def cache_path() -> str:
@@ -66,7 +70,7 @@ def time_schedule(plan, psi, schedule: Schedule, steps: int, repeats: int = 2) -
     return best
 
 
-def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: int = 48,
+def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: int = 120,
          use_cache: bool = True, log=None) -> Tuple[Schedule, Dict[str, float]]:
     """Pick the fastest schedule for this plan's mesh and dtype; set it on the plan.
 
@@ -76,7 +80,7 @@ def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: i
     arch = torch.cuda.get_device_properties(psi.device).gcnArchName.split(":")[0]
     key = _key(arch, plan.dtype, plan.problem.nx, plan.problem.ny)
     db = _load() if use_cache else {}
-    if use_cache and key in db:
+    if use_cache and key in db and len(db[key].get("schedule", [])) == 4:
         sched = tuple(db[key]["schedule"])
         plan.set_schedule(*sched)
         return sched, db[key].get("table", {})
@@ -87,7 +91,8 @@ def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: i
         ms = time_schedule(plan, scratch, cand, steps)
         table[",".join(map(str, cand))] = ms
         if log:
-            log(f"autotune {key} S={cand[0]} seg={cand[1]} ppl={cand[2]}: {ms:.3f} ms")
+            log(f"autotune {key} S={cand[0]} seg={cand[1]} ppl={cand[2]} store={cand[3]}: "
+                f"{ms:.3f} ms")
         if best is None or ms < table[",".join(map(str, best))]:
             best = cand
     del scratch

@@ -21,9 +21,7 @@ struct tsq_plan {
     tsq_problem p;
     double Jx, Jy, eps0;
     tsq::Coef64 oxh, oyh, ox2, oy2;
-    int steps_per_pass;   // 0 = default
-    int seg_rows;         // 0 = default
-    int ppl;              // 0 = default
+    tsq_schedule sched;   // resolved (segment_rows may stay 0 = per launch)
     size_t sites, elem, pelem;
     size_t off_psi2, off_ptab, off_scratch, ws_bytes;
     const void* ws_bound;
@@ -66,9 +64,18 @@ constexpr size_t kScratchBytes = (2 * tsq::kReduceBlocks + 2) * sizeof(double);
 // height: as many wavefront tiles as the device holds resident at once (one
 // round, no tail of a partly filled second round), each segment at least 2K
 // row pairs long so the discarded warm-up pairs stay below half the work.
-int default_steps_per_pass(const tsq_plan* p) {
-    (void)p;
-    return tsq::kMaxSteps;
+constexpr int kDefaultSteps = 4;
+
+// Fill the zero fields of a requested schedule with defaults; false if the
+// combination has no kernel instance.
+bool resolve_schedule(const tsq_schedule& in, tsq_schedule& out) {
+    out = in;
+    if (out.steps_per_pass == 0) out.steps_per_pass = kDefaultSteps;
+    if (out.phase_store == 0) out.phase_store = out.steps_per_pass <= tsq::kMaxRegSteps ? 1 : 2;
+    if (out.pairs_per_lane == 0) out.pairs_per_lane = 1;
+    if (out.phase_store == 1 && out.steps_per_pass > tsq::kMaxRegSteps) return false;
+    if (out.phase_store == 2 && out.pairs_per_lane != 1) return false;
+    return true;
 }
 
 struct DeviceShape {
@@ -90,25 +97,25 @@ int device_cus() {
     return g_dev.cus;
 }
 
-int occupancy_cached(int dtype, int steps, bool last, int ppl) {
-    // [dtype][steps][last][ppl]; 0 = not yet queried
-    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3];
-    std::atomic<int>& slot = table[dtype & 1][steps][last ? 1 : 0][ppl];
+int occupancy_cached(int dtype, int steps, bool last, int ppl, bool lds) {
+    // [dtype][steps][last][ppl][lds]; 0 = not yet queried
+    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3][2];
+    std::atomic<int>& slot = table[dtype & 1][steps][last ? 1 : 0][ppl][lds ? 1 : 0];
     int v = slot.load(std::memory_order_relaxed);
     if (v == 0) {
-        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl);
+        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl, lds);
         if (v <= 0) v = 1;
         slot.store(v, std::memory_order_relaxed);
     }
     return v;
 }
 
-int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl) {
+int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl, bool lds) {
     const tsq::MarchGeometry g = tsq::march_geometry(p->p.nx, p->p.ny, steps, last, ppl, 2);
     int cus = device_cus();
     if (cus <= 0) cus = 256;
     const long long slots =
-        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl) * tsq::kWavesPerBlock;
+        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl, lds) * tsq::kWavesPerBlock;
     const long long pairs = p->p.ny / 2;
     long long segs = slots / g.nstrips;
     if (segs < 1) segs = 1;
@@ -155,11 +162,6 @@ int64_t run_passes(const std::vector<Run>& runs) {
     int64_t n = 0;
     for (const Run& r : runs) n += r.count;
     return n;
-}
-
-int pairs_per_lane(const tsq_plan* p) {
-    if (p->ppl) return p->ppl;
-    return p->p.dtype == TSQ_C64 ? 2 : 1;
 }
 
 int check_ws(const tsq_plan* plan, const void* ws, size_t ws_bytes) {
@@ -214,9 +216,7 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
     p->oyh = block_coef(h, p->Jy, hb);
     p->ox2 = block_coef(pr->dt, p->Jx, hb);
     p->oy2 = block_coef(pr->dt, p->Jy, hb);
-    p->steps_per_pass = 0;
-    p->seg_rows = 0;
-    p->ppl = 0;
+    resolve_schedule(tsq_schedule{0, 0, 0, 0}, p->sched);
     p->sites = (size_t)pr->nx * (size_t)pr->ny;
     p->elem = pr->dtype == TSQ_C128 ? 16 : 8;
     p->pelem = 16;  // complex128: exp(-i phi); complex64: hi + lo complex floats
@@ -240,28 +240,30 @@ int tsq_workspace_size(const tsq_plan* plan, size_t* bytes) {
     return ok();
 }
 
-int tsq_plan_set_schedule(tsq_plan* plan, int32_t steps_per_pass, int32_t segment_rows,
-                          int32_t pairs_per_lane_) {
-    if (!plan) return fail(TSQ_ERR_ARG, "null plan");
-    if (pairs_per_lane_ < 0 || pairs_per_lane_ > 2)
-        return fail(TSQ_ERR_ARG, "pairs_per_lane %d outside 0..2", pairs_per_lane_);
-    if (steps_per_pass < 0 || steps_per_pass > tsq::kMaxSteps)
-        return fail(TSQ_ERR_ARG, "steps_per_pass %d outside 0..%d", steps_per_pass, tsq::kMaxSteps);
-    if (segment_rows < 0 || (segment_rows & 1))
-        return fail(TSQ_ERR_ARG, "segment_rows %d must be even and >= 0", segment_rows);
-    plan->steps_per_pass = steps_per_pass;
-    plan->seg_rows = segment_rows;
-    plan->ppl = pairs_per_lane_;
+int tsq_plan_set_schedule(tsq_plan* plan, const tsq_schedule* sc) {
+    if (!plan || !sc) return fail(TSQ_ERR_ARG, "null plan or schedule");
+    if (sc->steps_per_pass < 0 || sc->steps_per_pass > tsq::kMaxSteps)
+        return fail(TSQ_ERR_ARG, "steps_per_pass %d outside 0..%d", sc->steps_per_pass,
+                    tsq::kMaxSteps);
+    if (sc->segment_rows < 0 || (sc->segment_rows & 1))
+        return fail(TSQ_ERR_ARG, "segment_rows %d must be even and >= 0", sc->segment_rows);
+    if (sc->pairs_per_lane < 0 || sc->pairs_per_lane > 2)
+        return fail(TSQ_ERR_ARG, "pairs_per_lane %d outside 0..2", sc->pairs_per_lane);
+    if (sc->phase_store < 0 || sc->phase_store > 2)
+        return fail(TSQ_ERR_ARG, "phase_store %d outside 0..2", sc->phase_store);
+    tsq_schedule r;
+    if (!resolve_schedule(*sc, r))
+        return fail(TSQ_ERR_ARG,
+                    "no kernel for steps_per_pass %d, pairs_per_lane %d, phase_store %d "
+                    "(registers hold at most %d steps; LDS needs 1 pair per lane)",
+                    r.steps_per_pass, r.pairs_per_lane, r.phase_store, tsq::kMaxRegSteps);
+    plan->sched = r;
     return ok();
 }
 
-int tsq_plan_get_schedule(const tsq_plan* plan, int32_t* steps_per_pass, int32_t* segment_rows,
-                          int32_t* pairs_per_lane_) {
-    if (!plan || !steps_per_pass || !segment_rows || !pairs_per_lane_)
-        return fail(TSQ_ERR_ARG, "null argument");
-    *steps_per_pass = plan->steps_per_pass ? plan->steps_per_pass : default_steps_per_pass(plan);
-    *segment_rows = plan->seg_rows;
-    *pairs_per_lane_ = pairs_per_lane(plan);
+int tsq_plan_get_schedule(const tsq_plan* plan, tsq_schedule* sc) {
+    if (!plan || !sc) return fail(TSQ_ERR_ARG, "null argument");
+    *sc = plan->sched;
     return ok();
 }
 
@@ -269,8 +271,7 @@ int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int3
     if (!plan || !passes || !copy_back) return fail(TSQ_ERR_ARG, "null argument");
     if (steps < 0) return fail(TSQ_ERR_ARG, "steps must be >= 0 (%lld)", (long long)steps);
     std::vector<Run> runs;
-    const int S = plan->steps_per_pass ? plan->steps_per_pass : default_steps_per_pass(plan);
-    const bool cb = steps > 0 && pass_runs(steps, S, runs);
+    const bool cb = steps > 0 && pass_runs(steps, plan->sched.steps_per_pass, runs);
     *passes = run_passes(runs);
     *copy_back = cb ? 1 : 0;
     return ok();
@@ -303,8 +304,9 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
     void* buf[2] = {psi, w + plan->off_psi2};
-    const int S = plan->steps_per_pass ? plan->steps_per_pass : default_steps_per_pass(plan);
-    const int ppl = pairs_per_lane(plan);
+    const int S = plan->sched.steps_per_pass;
+    const int ppl = plan->sched.pairs_per_lane;
+    const bool lds = plan->sched.phase_store == 2;
 
     std::vector<Run> runs;
     const bool copy_back = pass_runs(steps, S, runs);
@@ -315,6 +317,7 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
     d.nx = plan->p.nx;
     d.ny = plan->p.ny;
     d.pairs_per_lane = ppl;
+    d.phase_lds = lds;
     d.oxh = plan->oxh;
     d.oyh = plan->oyh;
     d.ox2 = plan->ox2;
@@ -327,8 +330,9 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
             d.steps = r.size;
             d.first = (i == 0);
             d.last = (i + 1 == npasses);
-            d.seg_rows = plan->seg_rows ? plan->seg_rows
-                                        : default_seg_rows(plan, d.steps, d.last, ppl);
+            d.seg_rows = plan->sched.segment_rows
+                             ? plan->sched.segment_rows
+                             : default_seg_rows(plan, d.steps, d.last, ppl, lds);
             hipError_t e = tsq::launch_pass(plan->p.dtype, d, s);
             if (e != hipSuccess)
                 return fail(TSQ_ERR_DEVICE, "step pass launch: %s", hipGetErrorString(e));

@@ -24,11 +24,13 @@ struct PassDesc {
     bool last;            // the pass ends the evolution: it appends the final O(h)
     int seg_rows;         // rows per wavefront segment (even)
     int pairs_per_lane;   // 1 or 2 x-pairs held by each lane
+    bool phase_lds;       // phase ring in LDS (else registers)
     Coef64 oxh, oyh;      // tau = dt/2 along x, y
     Coef64 ox2, oy2;      // tau = dt along x, y
 };
 
-constexpr int kMaxSteps = 4;
+constexpr int kMaxSteps = 8;     // deepest fusion (phase ring in LDS)
+constexpr int kMaxRegSteps = 4;  // deepest fusion with the phase ring in registers
 constexpr int kWaveSize = 64;
 constexpr int kWavesPerBlock = 4;
 
@@ -45,7 +47,8 @@ MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per
 
 // Resident blocks per compute unit of one march kernel instance (0 if the
 // query fails); used to size segments so a pass is one round of resident waves.
-int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane);
+int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds);
+bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds);
 
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long sites,

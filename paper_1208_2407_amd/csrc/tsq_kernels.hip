@@ -25,6 +25,8 @@
 // through the same operations in the same order whatever the strip, segment
 // and S, so results are bitwise independent of the schedule.
 
+#include <utility>
+
 #include "tsq_internal.h"
 
 namespace tsq {
@@ -167,6 +169,11 @@ __device__ __forceinline__ void phase_row(Row<R, SPL>& w, const PT* p) {
     for (int i = 0; i < SPL; ++i) apply_phase(w.re[i], w.im[i], p[i]);
 }
 
+template <class PT, int SPL>
+struct PhasePair {
+    PT top[SPL], bot[SPL];
+};
+
 template <class R>
 struct MarchArgs {
     const void* src;
@@ -183,7 +190,53 @@ __device__ __forceinline__ int wrap(long long v, int n) {
     return (int)(m < 0 ? m + n : m);
 }
 
-template <class T, int S, bool LAST, int PPL>
+// One iteration of the S-stage pipeline.  On entry (it, ib) is the row pair t
+// just loaded; stage k completes pair t-1-k: the odd factors on its boundary
+// with pair t-k (whose top row arrives as `it`), then, for k < S, the even
+// factors and the phase on the pair itself (phase rows from `phase(k)`).
+// Stage K-1 = S of the last pass applies only the closing odd factors.  On
+// exit (it, ib) is pair t-K, finished.
+template <int S, int K, class R, int SPL, class PT, class PhaseFn>
+__device__ __forceinline__ void pipeline_step(Row<R, SPL> (&ht)[K], Row<R, SPL> (&hb)[K],
+                                              Row<R, SPL>& it, Row<R, SPL>& ib,
+                                              const MarchArgs<R>& a, PhaseFn&& phase) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        R oxs, oxd, oys, oyd;
+        if (k == 0) {
+            oxs = a.o1xs; oxd = a.o1xd; oys = a.o1ys; oyd = a.o1yd;
+        } else if (k < S) {
+            oxs = a.o2xs; oxd = a.o2xd; oys = a.o2ys; oyd = a.o2yd;
+        } else {
+            oxs = a.ehxs; oxd = a.ehxd; oys = a.ehys; oyd = a.ehyd;
+        }
+        odd_x(hb[k], oxs, oxd);
+        odd_x(it, oxs, oxd);
+        pair_y(hb[k], it, oys, oyd);
+        if (k < S) {
+            const PhasePair<PT, SPL> ph = phase(k);
+            even_x(ht[k], a.ehxs, a.ehxd);
+            even_x(hb[k], a.ehxs, a.ehxd);
+            pair_y(ht[k], hb[k], a.ehys, a.ehyd);
+            phase_row(ht[k], ph.top);
+            phase_row(hb[k], ph.bot);
+            pair_y(ht[k], hb[k], a.ehys, a.ehyd);
+            even_x(ht[k], a.ehxs, a.ehxd);
+            even_x(hb[k], a.ehxs, a.ehxd);
+        }
+        Row<R, SPL> ot = ht[k], ob = hb[k];
+        ht[k] = it;
+        hb[k] = ib;
+        it = ot;
+        ib = ob;
+    }
+}
+
+// Phase factors of the S row pairs inside the pipeline, plus the pair entering
+// it, are held either in a register ring (LDS = false; the march loop is
+// unrolled by the ring length so slot indices are static) or in a per-lane
+// LDS ring (LDS = true; dynamic slots, no unrolling, for deep pipelines).
+template <class T, int S, bool LAST, int PPL, bool LDS>
 __global__ void __launch_bounds__(kWaveSize * kWavesPerBlock)
 march_kernel(const MarchArgs<typename T::R> a) {
     using R = typename T::R;
@@ -191,6 +244,8 @@ march_kernel(const MarchArgs<typename T::R> a) {
     constexpr int SPL = 2 * PPL;
     constexpr int K = S + (LAST ? 1 : 0);
     constexpr int HL = (K + PPL - 1) / PPL;
+    constexpr int NL = LDS ? S + 1 : 1;  // LDS ring slots (1 = unused)
+    __shared__ PT lring[LDS ? kWavesPerBlock : 1][NL][2][SPL][kWaveSize];
 
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = threadIdx.x / kWaveSize;
@@ -222,6 +277,7 @@ march_kernel(const MarchArgs<typename T::R> a) {
     const int hp = ny >> 1;
     const int q0 = seg * (a.seg_rows >> 1);
     const int q1 = min(q0 + (a.seg_rows >> 1), hp);
+    const int tfirst = q0 - K;
     const int tlast = q1 - 1 + K;
 
     Row<R, SPL> ht[K], hb[K];
@@ -234,14 +290,6 @@ march_kernel(const MarchArgs<typename T::R> a) {
         }
     }
 
-    // Phase factors ride in a register ring of NP slots: the pair a stage
-    // completes was loaded (with its psi) one iteration before it entered the
-    // pipeline, so the S stages use S slots, one slot waits and one is in
-    // flight.  The march loop is unrolled by NP so every slot index is static.
-    constexpr int NP = S + 2;
-    PT pr[NP][2][SPL];
-    Row<R, SPL> nt, nbm;
-
     auto load_psi = [&](int t, Row<R, SPL>& top, Row<R, SPL>& bot) {
         const int r0 = wrap(2LL * t, ny);
 #pragma unroll
@@ -250,76 +298,83 @@ march_kernel(const MarchArgs<typename T::R> a) {
             load_pair(a.src, (long long)(r0 + 1) * nx + col[p], bot, p);
         }
     };
-    auto load_phase = [&](int t, PT (&slot)[2][SPL]) {
+    auto load_phase = [&](int t) {
         const int r0 = wrap(2LL * t, ny);
         const PT* P0 = reinterpret_cast<const PT*>(a.ptab) + (long long)r0 * nx;
         const PT* P1 = P0 + nx;
+        PhasePair<PT, SPL> ph;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-            slot[0][2 * p] = P0[col[p]];
-            slot[0][2 * p + 1] = P0[col[p] + 1];
-            slot[1][2 * p] = P1[col[p]];
-            slot[1][2 * p + 1] = P1[col[p] + 1];
+            ph.top[2 * p] = P0[col[p]];
+            ph.top[2 * p + 1] = P0[col[p] + 1];
+            ph.bot[2 * p] = P1[col[p]];
+            ph.bot[2 * p + 1] = P1[col[p] + 1];
+        }
+        return ph;
+    };
+    auto store_out = [&](int qo, const Row<R, SPL>& top, const Row<R, SPL>& bot) {
+        if (qo < q0) return;
+        const long long r0 = 2LL * qo;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            if (keep[p]) {
+                store_pair(a.dst, r0 * nx + col[p], top, p);
+                store_pair(a.dst, (r0 + 1) * nx + col[p], bot, p);
+            }
         }
     };
 
-    const int tfirst = q0 - K;
+    Row<R, SPL> nt, nbm;  // psi of the next pair (prefetched one iteration ahead)
     load_psi(tfirst, nt, nbm);
-    load_phase(tfirst, pr[0]);
 
-    for (int tb = tfirst; tb <= tlast; tb += NP) {
+    if constexpr (!LDS) {
+        constexpr int NP = S + 2;
+        PhasePair<PT, SPL> pr[NP];
+        pr[0] = load_phase(tfirst);
+        for (int tb = tfirst; tb <= tlast; tb += NP) {
 #pragma unroll
-        for (int u = 0; u < NP; ++u) {
-            const int t = tb + u;
-            if (t > tlast) break;  // uniform per wavefront
+            for (int u = 0; u < NP; ++u) {
+                const int t = tb + u;
+                if (t > tlast) break;  // uniform per wavefront
+                Row<R, SPL> it = nt, ib = nbm;
+                if (t < tlast) {
+                    load_psi(t + 1, nt, nbm);
+                    pr[(u + 1) % NP] = load_phase(t + 1);
+                }
+                pipeline_step<S, K, R, SPL, PT>(ht, hb, it, ib, a,
+                                                [&](int k) { return pr[(u - 1 - k + 2 * NP) % NP]; });
+                store_out(t - K, it, ib);
+            }
+        }
+    } else {
+        PhasePair<PT, SPL> pn = load_phase(tfirst);  // next pair's phase, in flight
+        PT* ring = &lring[LDS ? wave : 0][0][0][0][lane];
+        constexpr int SLOT = 2 * SPL * kWaveSize;  // PT elements per slot
+        int wslot = 0;                             // slot of pair t
+        for (int t = tfirst; t <= tlast; ++t) {
             Row<R, SPL> it = nt, ib = nbm;
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                ring[wslot * SLOT + i * kWaveSize] = pn.top[i];
+                ring[wslot * SLOT + (SPL + i) * kWaveSize] = pn.bot[i];
+            }
             if (t < tlast) {
                 load_psi(t + 1, nt, nbm);
-                load_phase(t + 1, pr[(u + 1) % NP]);
+                pn = load_phase(t + 1);
             }
+            pipeline_step<S, K, R, SPL, PT>(ht, hb, it, ib, a, [&](int k) {
+                int slot = wslot - 1 - k;
+                if (slot < 0) slot += NL;
+                PhasePair<PT, SPL> ph;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                R oxs, oxd, oys, oyd;
-                if (k == 0) {
-                    oxs = a.o1xs; oxd = a.o1xd; oys = a.o1ys; oyd = a.o1yd;
-                } else if (k < S) {
-                    oxs = a.o2xs; oxd = a.o2xd; oys = a.o2ys; oyd = a.o2yd;
-                } else {
-                    oxs = a.ehxs; oxd = a.ehxd; oys = a.ehys; oyd = a.ehyd;
+                for (int i = 0; i < SPL; ++i) {
+                    ph.top[i] = ring[slot * SLOT + i * kWaveSize];
+                    ph.bot[i] = ring[slot * SLOT + (SPL + i) * kWaveSize];
                 }
-                // odd factors on the boundary between pair (t-1-k) and the incoming pair
-                odd_x(hb[k], oxs, oxd);
-                odd_x(it, oxs, oxd);
-                pair_y(hb[k], it, oys, oyd);
-                if (k < S) {
-                    // even factors, phase, even factors on the completed pair t-1-k
-                    const int slot = (u - 1 - k + 2 * NP) % NP;
-                    even_x(ht[k], a.ehxs, a.ehxd);
-                    even_x(hb[k], a.ehxs, a.ehxd);
-                    pair_y(ht[k], hb[k], a.ehys, a.ehyd);
-                    phase_row(ht[k], pr[slot][0]);
-                    phase_row(hb[k], pr[slot][1]);
-                    pair_y(ht[k], hb[k], a.ehys, a.ehyd);
-                    even_x(ht[k], a.ehxs, a.ehxd);
-                    even_x(hb[k], a.ehxs, a.ehxd);
-                }
-                Row<R, SPL> ot = ht[k], ob = hb[k];
-                ht[k] = it;
-                hb[k] = ib;
-                it = ot;
-                ib = ob;
-            }
-            const int qo = t - K;
-            if (qo >= q0) {
-                const long long r0 = 2LL * qo;
-#pragma unroll
-                for (int p = 0; p < PPL; ++p) {
-                    if (keep[p]) {
-                        store_pair(a.dst, r0 * nx + col[p], it, p);
-                        store_pair(a.dst, (r0 + 1) * nx + col[p], ib, p);
-                    }
-                }
-            }
+                return ph;
+            });
+            store_out(t - K, it, ib);
+            wslot = (wslot + 1 == NL) ? 0 : wslot + 1;
         }
     }
 }
@@ -451,65 +506,47 @@ MarchArgs<R> make_args(const PassDesc& d, const MarchGeometry& g) {
     return a;
 }
 
-template <class T, int S, bool LAST, int PPL>
-int occupancy_march() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, march_kernel<T, S, LAST, PPL>,
-                                                     kWaveSize * kWavesPerBlock, 0) != hipSuccess)
-        return 0;
-    return n;
+template <class T, int S, bool LAST, int PPL, bool LDS>
+const void* kernel_ptr() {
+    return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS>);
 }
 
-template <class T, int S, bool LAST>
-int occupancy_ppl(int ppl) {
-    return ppl == 2 ? occupancy_march<T, S, LAST, 2>() : occupancy_march<T, S, LAST, 1>();
+// Instances: register ring for 1..4 steps per pass (1 or 2 pairs per lane),
+// LDS ring for 1..kMaxSteps steps per pass (1 pair per lane).
+template <class T, bool LAST, int PPL, bool LDS, int... Ss>
+const void* pick_steps(int steps, std::integer_sequence<int, Ss...>) {
+    const void* f = nullptr;
+    ((steps == Ss + 1 ? (f = kernel_ptr<T, Ss + 1, LAST, PPL, LDS>(), 0) : 0), ...);
+    return f;
 }
 
-template <class T, int S>
-int occupancy_last(bool last, int ppl) {
-    return last ? occupancy_ppl<T, S, true>(ppl) : occupancy_ppl<T, S, false>(ppl);
+template <class T, bool LAST>
+const void* pick_variant(int steps, int ppl, bool lds) {
+    if (lds) {
+        if (ppl != 1) return nullptr;
+        return pick_steps<T, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxSteps>());
+    }
+    if (ppl == 2)
+        return pick_steps<T, LAST, 2, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
+    return pick_steps<T, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
 }
 
 template <class T>
-int occupancy_steps(int steps, bool last, int ppl) {
-    switch (steps) {
-        case 1: return occupancy_last<T, 1>(last, ppl);
-        case 2: return occupancy_last<T, 2>(last, ppl);
-        case 3: return occupancy_last<T, 3>(last, ppl);
-        case 4: return occupancy_last<T, 4>(last, ppl);
-        default: return 0;
-    }
+const void* pick_kernel(int steps, bool last, int ppl, bool lds) {
+    return last ? pick_variant<T, true>(steps, ppl, lds) : pick_variant<T, false>(steps, ppl, lds);
 }
 
-template <class T, int S, bool LAST, int PPL>
-hipError_t launch_march(const PassDesc& d, hipStream_t s) {
-    const MarchGeometry g = march_geometry(d.nx, d.ny, S, LAST, PPL, d.seg_rows);
-    const MarchArgs<typename T::R> a = make_args<typename T::R>(d, g);
-    hipLaunchKernelGGL((march_kernel<T, S, LAST, PPL>), dim3(g.blocks),
-                       dim3(kWaveSize * kWavesPerBlock), 0, s, a);
-    return hipGetLastError();
+const void* march_kernel_ptr(int dtype, int steps, bool last, int ppl, bool lds) {
+    return dtype == 1 ? pick_kernel<C128>(steps, last, ppl, lds)
+                      : pick_kernel<C64>(steps, last, ppl, lds);
 }
 
-template <class T, int S, bool LAST>
-hipError_t launch_ppl(const PassDesc& d, hipStream_t s) {
-    return d.pairs_per_lane == 2 ? launch_march<T, S, LAST, 2>(d, s)
-                                 : launch_march<T, S, LAST, 1>(d, s);
-}
-
-template <class T, int S>
-hipError_t launch_last(const PassDesc& d, hipStream_t s) {
-    return d.last ? launch_ppl<T, S, true>(d, s) : launch_ppl<T, S, false>(d, s);
-}
-
-template <class T>
-hipError_t launch_steps(const PassDesc& d, hipStream_t s) {
-    switch (d.steps) {
-        case 1: return launch_last<T, 1>(d, s);
-        case 2: return launch_last<T, 2>(d, s);
-        case 3: return launch_last<T, 3>(d, s);
-        case 4: return launch_last<T, 4>(d, s);
-        default: return hipErrorInvalidValue;
-    }
+template <class R>
+hipError_t launch_with(const void* f, const PassDesc& d, hipStream_t s) {
+    const MarchGeometry g = march_geometry(d.nx, d.ny, d.steps, d.last, d.pairs_per_lane, d.seg_rows);
+    MarchArgs<R> a = make_args<R>(d, g);
+    void* params[] = {&a};
+    return hipLaunchKernel(f, dim3(g.blocks), dim3(kWaveSize * kWavesPerBlock), params, 0, s);
 }
 
 }  // namespace
@@ -541,13 +578,26 @@ hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long 
     return hipGetLastError();
 }
 
-int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane) {
-    return dtype == 1 ? occupancy_steps<C128>(steps, last, pairs_per_lane)
-                      : occupancy_steps<C64>(steps, last, pairs_per_lane);
+bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds) {
+    return march_kernel_ptr(dtype, steps, last, pairs_per_lane, phase_lds) != nullptr;
+}
+
+int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds) {
+    const void* f = march_kernel_ptr(dtype, steps, last, pairs_per_lane, phase_lds);
+    if (!f) return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kWaveSize * kWavesPerBlock, 0) !=
+        hipSuccess)
+        return 0;
+    return n;
 }
 
 hipError_t launch_pass(int dtype, const PassDesc& d, hipStream_t s) {
-    return dtype == 1 ? launch_steps<C128>(d, s) : launch_steps<C64>(d, s);
+    const void* f = march_kernel_ptr(dtype, d.steps, d.last, d.pairs_per_lane, d.phase_lds);
+    if (!f) return hipErrorInvalidValue;
+    hipError_t e = dtype == 1 ? launch_with<double>(f, d, s) : launch_with<float>(f, d, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
 }
 
 hipError_t launch_observables(int dtype, const void* psi, const double* V, int nx, int ny,

@@ -30,12 +30,12 @@ def as_input(psi0: np.ndarray, dtype: str) -> np.ndarray:
 
 def gpu_evolve(psi0: np.ndarray, V: np.ndarray, dt: float, steps: int, dtype: str,
                steps_per_pass: int = 0, segment_rows: int = 0, pairs_per_lane: int = 0,
-               **consts) -> np.ndarray:
+               phase_store: int = 0, **consts) -> np.ndarray:
     ny, nx = psi0.shape
     psi = torch.from_numpy(np.ascontiguousarray(psi0)).to(TORCH_DT[dtype]).cuda()
     Vd = torch.from_numpy(np.ascontiguousarray(V, dtype=np.float64)).cuda()
     plan = tsq.Plan(nx, ny, dt, dtype, device=psi.device, **consts)
-    plan.set_schedule(steps_per_pass, segment_rows, pairs_per_lane)
+    plan.set_schedule(steps_per_pass, segment_rows, pairs_per_lane, phase_store)
     plan.set_potential(Vd)
     plan.evolve(psi, steps)
     torch.cuda.synchronize()

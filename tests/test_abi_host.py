@@ -68,17 +68,26 @@ def test_plan_create_accepts_negative_dt_and_reports_workspace():
             tsq.tsq_plan_destroy(h)
 
 
+def sched(*v):
+    return tsq.tsq_schedule(*v)
+
+
 def test_schedule_validation():
     h = tsq.tsq_plan_create(problem())
     try:
-        tsq.tsq_plan_set_schedule(h, 3, 64, 2)
-        assert tsq.tsq_plan_get_schedule(h) == (3, 64, 2)
-        tsq.tsq_plan_set_schedule(h, 0, 0, 0)
-        assert tsq.tsq_plan_get_schedule(h)[2] in (1, 2)
-        for bad in ((-1, 0, 0), (9, 0, 0), (2, 7, 0), (2, -2, 0), (1, 0, 3)):
+        tsq.tsq_plan_set_schedule(h, sched(3, 64, 2, 1))
+        assert tsq.tsq_plan_get_schedule(h).as_tuple() == (3, 64, 2, 1)
+        tsq.tsq_plan_set_schedule(h, sched(0, 0, 0, 0))
+        assert tsq.tsq_plan_get_schedule(h).as_tuple() == (4, 0, 1, 1)
+        tsq.tsq_plan_set_schedule(h, sched(7, 0, 0, 0))
+        assert tsq.tsq_plan_get_schedule(h).as_tuple() == (7, 0, 1, 2)
+        before = tsq.tsq_plan_get_schedule(h).as_tuple()
+        for bad in ((-1, 0, 0, 0), (9, 0, 0, 0), (2, 7, 0, 0), (2, -2, 0, 0), (1, 0, 3, 0),
+                    (1, 0, 0, 3), (5, 0, 0, 1), (2, 0, 2, 2), (8, 0, 2, 0)):
             with pytest.raises(tsq.TsqError) as ei:
-                tsq.tsq_plan_set_schedule(h, *bad)
+                tsq.tsq_plan_set_schedule(h, sched(*bad))
             assert ei.value.status == -1
+            assert tsq.tsq_plan_get_schedule(h).as_tuple() == before
     finally:
         tsq.tsq_plan_destroy(h)
 
@@ -107,12 +116,12 @@ def test_calls_reject_null_and_out_of_order_before_any_launch():
 @pytest.mark.parametrize("S,steps,passes,copy", [
     (4, 1000, 250, False), (4, 100, 26, False), (1, 7, 7, True), (4, 1, 1, True),
     (4, 3, 2, False), (3, 0, 0, False), (2, 5, 4, False), (1, 8, 8, False),
-    (4, 10**12 + 4, 250000000002, False),
+    (4, 10**12 + 4, 250000000002, False), (8, 1000, 126, False), (7, 14, 2, False),
 ])
 def test_pass_count(S, steps, passes, copy):
     h = tsq.tsq_plan_create(problem())
     try:
-        tsq.tsq_plan_set_schedule(h, S, 0, 0)
+        tsq.tsq_plan_set_schedule(h, sched(S, 0, 0, 0))
         assert tsq.tsq_evolve_passes(h, steps) == (passes, copy)
     finally:
         tsq.tsq_plan_destroy(h)

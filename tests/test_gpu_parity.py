@@ -40,22 +40,30 @@ def test_gaussian_in_well_256(dtype):
 SHAPES = [(2, 2), (4, 6), (130, 66), (300, 258), (258, 300), (66, 1030)]
 
 
+def variants(S):
+    """(pairs_per_lane, phase_store) kernel variants built for S steps per pass."""
+    v = [(1, 2)]
+    if S <= 4:
+        v += [(1, 1), (2, 1)]
+    return v
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("S", [1, 2, 3, 4])
+@pytest.mark.parametrize("S", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_ragged_meshes(shape, S, dtype):
     """Sides that are not multiples of the strip or segment, every steps-per-pass value,
-    both lane widths, odd and even step counts, anisotropic constants."""
+    every kernel variant, odd and even step counts, anisotropic constants."""
     nx, ny = shape
     psi0 = wl.random_state(nx, ny, 7 + nx)
     V = wl.random_potential(nx, ny, 8 + ny, scale=0.5)
-    for steps in (1, 7):
+    for steps in (1, 7, 2 * S + 1):
         want = oracle_evolve(psi0, V, 0.11, steps, dtype, **ANISO)
-        for ppl in (1, 2):
+        for ppl, store in variants(S):
             got = gpu_evolve(psi0, V, 0.11, steps, dtype, steps_per_pass=S, segment_rows=16,
-                             pairs_per_lane=ppl, **ANISO)
+                             pairs_per_lane=ppl, phase_store=store, **ANISO)
             err = rel_l2(got, want)
-            assert err <= TOL[dtype], (shape, S, ppl, steps, err)
+            assert err <= TOL[dtype], (shape, S, ppl, store, steps, err)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -65,13 +73,14 @@ def test_schedule_does_not_change_a_bit(dtype):
     nx, ny = 300, 258
     psi0 = wl.random_state(nx, ny, 3)
     V = wl.random_potential(nx, ny, 4)
-    ref = gpu_evolve(psi0, V, 0.09, 11, dtype, steps_per_pass=1, segment_rows=2, pairs_per_lane=1)
-    for S in (1, 2, 3, 4):
+    ref = gpu_evolve(psi0, V, 0.09, 11, dtype, steps_per_pass=1, segment_rows=2, pairs_per_lane=1,
+                     phase_store=1)
+    for S in range(1, 9):
         for seg in (2, 6, 64, 0):
-            for ppl in (1, 2):
+            for ppl, store in variants(S):
                 got = gpu_evolve(psi0, V, 0.09, 11, dtype, steps_per_pass=S, segment_rows=seg,
-                                 pairs_per_lane=ppl)
-                assert np.array_equal(got, ref), (S, seg, ppl)
+                                 pairs_per_lane=ppl, phase_store=store)
+                assert np.array_equal(got, ref), (S, seg, ppl, store)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
