@@ -21,29 +21,31 @@ _LIB = os.path.join(_HERE, "_build", "libtso_oracle.so")
 BC = {"periodic": 0, "closed": 1}
 
 
+def compile_library(src: str, out: str) -> str:
+    """gcc -O2 -fopenmp a C oracle source into a shared library."""
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the C oracle into oracle/_build/libtso_oracle.so (portable -O2, OpenMP)."""
     if not force and os.path.exists(_LIB):
         return _LIB
-    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-    tmp = _LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    return compile_library(_SRC, _LIB)
 
 
 _lib = None
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB):
-        build()
-    lib = ctypes.CDLL(_LIB)
+def load_library(path: str):
+    """A configured handle on an oracle library at `path` (the default build, or a
+    variant compiled by a test)."""
+    lib = ctypes.CDLL(path)
     d, i, ll, p = ctypes.c_double, ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p
     lib.tso_evolve.argtypes = [i, i, i, d, d, d, d, d, p, p, ll, i]
     lib.tso_evolve.restype = i
@@ -56,8 +58,16 @@ def _load():
     lib.tso_set_threads.restype = None
     lib.tso_max_threads.argtypes = []
     lib.tso_max_threads.restype = i
-    _lib = lib
     return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = load_library(_LIB)
+    return _lib
 
 
 def set_threads(n: int) -> None:
