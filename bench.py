@@ -31,9 +31,14 @@ def log(msg: str) -> None:
 
 
 def kernel_hash() -> str:
+    """sha256[:16] of the device sources (csrc/*.hip, *.hpp, *.h)."""
+    import glob
     h = hashlib.sha256()
-    for f in ("tsq_kernels.hip", "tsq_internal.h"):
-        with open(os.path.join(ROOT, "paper_1208_2407_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_1208_2407_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))
+                    + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -159,6 +164,132 @@ def profile_mode(p, psi0, V, args) -> int:
     return 0
 
 
+def run_batch(args) -> dict:
+    """512 independent complex64 problems (sides log-uniform in [64, 1024], rounded to
+    even; own potential, packets and dt), 500 steps each: one batched call (captured
+    HIP graph) against sequential plain tsq_evolve calls on the same GPU."""
+    import torch
+    import paper_1208_2407_amd as tsq
+    from paper_1208_2407_amd import workloads as wl
+
+    probs = wl.batch_problems(512, 4, 500, dtype="c64")
+    log(f"batch: generating {len(probs)} problems")
+    psi0s, Vs, plans = [], [], []
+    for q in probs:
+        psi0s.append(wl.initial_state(q, device="cuda", dtype=torch.complex64))
+        V = wl.potential(q, device="cuda")
+        pl = tsq.Plan(q.nx, q.ny, q.dt, "c64")
+        pl.set_potential(V)
+        Vs.append(V)
+        plans.append(pl)
+    steps = [q.steps for q in probs]
+    site_steps = sum(q.nx * q.ny * q.steps for q in probs)
+    sites = sum(q.nx * q.ny for q in probs)
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    # batch schedule: a short search over steps per pass (LDS ring, one pair per lane)
+    best = None
+    for S in ([int(args.schedule.split(",")[0])] if args.schedule else (2, 3, 4, 6)):
+        sched = (S, 0, 1, 2)
+        psis = [x.clone() for x in psi0s]
+        bt = tsq.Batch(plans, psis, steps, sched)
+        bt.launch(use_graph=True)
+        t = timed(lambda: bt.launch(use_graph=True), 1)
+        log(f"batch: S={S}: {t * 1e3:.1f} ms per call ({bt.info()[0]} launches)")
+        if best is None or t < best[0]:
+            best = (t, sched)
+        del bt, psis
+    sched = best[1]
+    psis = [x.clone() for x in psi0s]
+    bt = tsq.Batch(plans, psis, steps, sched)
+    launches, tiles = bt.info()
+    for _ in range(args.warmup):
+        bt.launch(use_graph=True)
+    t_batch = timed(lambda: bt.launch(use_graph=True), args.steps)
+    # sequential plain solves: each problem alone, same kernels and schedule
+    seq = [x.clone() for x in psi0s]
+    for pl in plans:
+        pl.set_schedule(*sched)
+
+    def sequential():
+        for pl, x, n in zip(plans, seq, steps):
+            pl.evolve(x, n)
+
+    sequential()
+    t_seq = timed(sequential, 1)
+    # the batched result equals each problem alone (bitwise), spot-checked
+    ref = [x.clone() for x in psi0s[:8]]
+    for pl, x, n in zip(plans[:8], ref, steps[:8]):
+        pl.evolve(x, n)
+    one = [x.clone() for x in psi0s]
+    bt1 = tsq.Batch(plans, one, steps, sched)
+    bt1.launch()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(one[:8], ref))
+    log(f"batch: {t_batch * 1e3:.1f} ms per call, sequential {t_seq * 1e3:.1f} ms, "
+        f"speedup {t_seq / t_batch:.2f}x, bitwise equal to alone: {same}")
+    return {
+        "metric": METRIC, "value": site_steps / t_batch, "unit": "site-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "batch512_c64_500steps", "problems": len(probs), "sites": sites,
+                   "site_steps_per_call": site_steps, "steps_per_pass": sched[0],
+                   "phase_store": "lds", "launches_per_call": launches, "tiles_per_call": tiles,
+                   "hip_graph": True},
+        "sequential": {"value": site_steps / t_seq, "ms_per_call": t_seq * 1e3},
+        "speedup_vs_sequential": t_seq / t_batch,
+        "bitwise_equal_to_alone": same,
+    }
+
+
+def run_served(args) -> dict:
+    """Poisson arrivals at 200 req/s for --serve-seconds seconds (sides log-uniform
+    128-4096, steps 100-2000, 80/20 complex64/complex128) replayed in real time into
+    the continuous-batching server; the FIFO one-at-a-time server on the first
+    --fifo-seconds of the same trace for comparison."""
+    import torch
+    from paper_1208_2407_amd import serve
+    from paper_1208_2407_amd import workloads as wl
+
+    trace = wl.request_trace(rate=200.0, duration=args.serve_seconds, seed=5)
+    offered = sum(r.problem.site_steps for r in trace) / args.serve_seconds
+    log(f"served: {len(trace)} requests over {args.serve_seconds} s, offered {offered:.3e} "
+        f"site-steps/s")
+    # warm the code paths
+    serve.Server(block_steps=args.block_steps).run(trace[:16], realtime=False)
+    srv = serve.Server(block_steps=args.block_steps)
+    st = srv.run(trace, realtime=True).summary()
+    log(f"served: {st}")
+    fifo_trace = [r for r in trace if r.arrival < args.fifo_seconds]
+    batched_prefix = serve.Server(block_steps=args.block_steps).run(fifo_trace).summary()
+    fifo = serve.serve_fifo(fifo_trace).summary()
+    log(f"served prefix ({args.fifo_seconds} s): batched {batched_prefix}")
+    log(f"served prefix ({args.fifo_seconds} s): fifo {fifo}")
+    return {
+        "metric": METRIC, "value": st["site_steps_per_s"], "unit": "site-steps/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": st["makespan_s"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128",
+        "data": "synthetic",
+        "config": {"workload": f"served_poisson200_{args.serve_seconds:g}s",
+                   "requests": len(trace), "offered_site_steps_per_s": offered,
+                   "block_steps": args.block_steps, "hbm_budget_bytes": srv.budget,
+                   "schedules": {k: list(v) for k, v in serve.SCHEDULES.items()}},
+        "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"],
+        "utilization": offered / st["site_steps_per_s"] if st["site_steps_per_s"] else None,
+        "served": st,
+        "fifo_comparison": {"trace_seconds": args.fifo_seconds, "batched": batched_prefix,
+                            "fifo": fifo},
+    }
+
+
 def cpu_baseline(p, psi0_host, V_host, sample_steps: int):
     import oracle
     oracle.build(force=False)
@@ -188,6 +319,14 @@ def main() -> int:
     ap.add_argument("--cpu-sample-steps", type=int, default=400)
     ap.add_argument("--dtypes", default="c64,c128")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--workload", default="mesh4096",
+                    choices=["mesh4096", "mesh32768", "batch512", "served"],
+                    help="mesh4096: the benchmark line; mesh32768: 32768^2 complex64, 200 "
+                         "steps; batch512: 512 uneven complex64 problems, 500 steps; "
+                         "served: Poisson request stream into the batching server")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--fifo-seconds", type=float, default=10.0)
+    ap.add_argument("--block-steps", type=int, default=24)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "
@@ -200,6 +339,28 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.workload == "batch512":
+        print(json.dumps(run_batch(args)), flush=True)
+        return 0
+    if args.workload == "served":
+        print(json.dumps(run_served(args)), flush=True)
+        return 0
+    if args.workload == "mesh32768":
+        p = wl.config("mesh32768_c64")
+        log("generating inputs on the device")
+        psi0 = wl.initial_state(p, device="cuda", dtype=torch.complex64)
+        V = wl.potential(p, device="cuda")
+        r = run_dtype("c64", p, psi0, V, args)
+        line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+                "data": "synthetic",
+                "config": {"workload": "packets_bumps_32768x32768_dt0.05_200steps",
+                           "mesh": [p.nx, p.ny], "time_steps_per_solve": p.steps, "dt": p.dt,
+                           **r["schedule"]},
+                "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
+        print(json.dumps(line), flush=True)
+        return 0
     p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 1000, "c64", name="packets_bumps_4096")
     log("generating inputs on the device")
     psi0 = wl.initial_state(p, device="cuda")

@@ -25,8 +25,9 @@
  *     Consecutive steps share their odd factors (Ox(h)Ox(h) = Ox(2h)); one
  *     tsq_evolve call therefore applies exactly U2(dt)^steps up to rounding.
  *   - Periodic boundaries: the odd pairs include (L-1, 0); both sides must be
- *     even.  Closed boundaries (hard walls, no wrap pair) are declared for a
- *     later version and currently return TSQ_ERR_UNSUPPORTED.
+ *     even.  Closed boundaries: hard walls, no pair crosses a wall, sides of
+ *     any length >= 2 (the printed H1/H2 of Sec. 2 are of this kind); the
+ *     diagonal keeps its full value at the walls.
  *
  * Memory and ownership
  *   - The caller owns all device memory: psi, V, and a workspace of
@@ -57,7 +58,7 @@
 extern "C" {
 #endif
 
-#define TSQ_ABI_VERSION 1
+#define TSQ_ABI_VERSION 2
 
 typedef enum {
     TSQ_OK = 0,
@@ -82,6 +83,9 @@ typedef struct {
     double dt;        /* time step; finite, any sign (negative evolves backwards) */
     int32_t bc;       /* tsq_bc */
     int32_t dtype;    /* tsq_dtype of psi */
+    int32_t order;    /* 2: U2(dt) per step (Eq. "secondorder"); 4: U4(dt) per step,
+                         U2(p dt)^2 U2((1-4p) dt) U2(p dt)^2, p = 1/(4 - 4^(1/3))
+                         (Eq. "fourthorder"); 0 means 2 */
 } tsq_problem;
 
 typedef struct tsq_plan tsq_plan; /* opaque, host memory */
@@ -96,8 +100,8 @@ const char* tsq_last_error(void);
 /* Validate a problem and build a plan: the FP64 rotation coefficients
  * (sin al and 1 - cos al = 2 sin^2(al/2) for tau = dt/2 and dt along each
  * axis) and a default schedule.  Host only; touches no device.
- * Errors: TSQ_ERR_ARG (null, bad constant), TSQ_ERR_SHAPE, TSQ_ERR_DTYPE,
- * TSQ_ERR_UNSUPPORTED (closed boundaries).  *out is set only on TSQ_OK. */
+ * Errors: TSQ_ERR_ARG (null, bad constant, order not 0/2/4), TSQ_ERR_SHAPE,
+ * TSQ_ERR_DTYPE.  *out is set only on TSQ_OK. */
 int tsq_plan_create(const tsq_problem* problem, tsq_plan** out);
 
 /* Free a plan (NULL is accepted). */
@@ -105,7 +109,8 @@ int tsq_plan_destroy(tsq_plan* plan);
 
 /* Bytes of device workspace the plan needs: a second psi buffer, the phase
  * table (complex128: one complex double per site; complex64: a hi/lo pair of
- * complex floats per site) and reduction scratch.  Host only. */
+ * complex floats per site; order 4 keeps two tables, for the sub-steps of
+ * p dt and (1-4p) dt) and reduction scratch.  Host only. */
 int tsq_workspace_size(const tsq_plan* plan, size_t* bytes);
 
 /* Schedule of the fused step kernel.  Every schedule applies the same
@@ -126,7 +131,8 @@ typedef struct {
  * tsq_plan_get_schedule returns the resolved values (segment_rows stays 0 when
  * it is sized per launch).  Errors: TSQ_ERR_ARG (null, value out of range, or
  * an unsupported combination: registers with more than 4 steps per pass, LDS
- * with 2 pairs per lane); the plan keeps its previous schedule. */
+ * with 2 pairs per lane, 2 pairs per lane on a closed mesh); the plan keeps
+ * its previous schedule. */
 int tsq_plan_set_schedule(tsq_plan* plan, const tsq_schedule* schedule);
 int tsq_plan_get_schedule(const tsq_plan* plan, tsq_schedule* schedule);
 
@@ -143,7 +149,7 @@ int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int3
 int tsq_set_potential(tsq_plan* plan, const double* V_dev, void* ws, size_t ws_bytes,
                       void* stream);
 
-/* Rows a1-a6: apply U2(dt)^steps to psi_dev in place (device, contiguous,
+/* Rows a1-a6: apply U2(dt)^steps (order 4: U4(dt)^steps) to psi_dev in place (device, contiguous,
  * 16-byte aligned).  steps == 0 returns TSQ_OK without a launch.
  * Errors: TSQ_ERR_ARG (null, steps < 0, misaligned psi), TSQ_ERR_STATE (no
  * potential set, or a different workspace), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
@@ -152,7 +158,8 @@ int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws
 
 /* Row a7: FP64 norm N = sum |psi_l|^2 and energy E = <psi|H|psi> / N of the
  * lattice Hamiltonian H = diag(V + eps0) - Jx (x-neighbours) - Jy
- * (y-neighbours), J_a = hbar^2/(2 m da^2), neighbours wrapping periodically.
+ * (y-neighbours), J_a = hbar^2/(2 m da^2), neighbours wrapping periodically
+ * (absent beyond closed walls).
  * Reduces in a fixed order (bitwise reproducible), uses the scratch part of
  * `ws` (it does not disturb the phase table), synchronises `stream` and
  * writes the two host doubles.  Errors: TSQ_ERR_ARG, TSQ_ERR_WORKSPACE,
@@ -160,6 +167,50 @@ int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws
 int tsq_observables(const tsq_plan* plan, const void* psi_dev, const double* V_dev,
                     double* norm_out, double* energy_out, void* ws, size_t ws_bytes,
                     void* stream);
+
+/* ---------------------------------------------------------------- batched form
+ * Many independent problems (each its own plan, psi, workspace and step
+ * count; Sec. 2's problem statement per problem) advanced together: every
+ * launch runs one pass of every problem that has one, as a fixed grid of
+ * wavefronts walking a device work list of tiles sorted by height.  Results
+ * are bitwise identical to tsq_evolve of each problem alone with the same
+ * schedule. */
+typedef struct tsq_batch tsq_batch; /* opaque, host memory */
+
+/* Build a batch of n problems (host only): problem i is plans[i] applied to
+ * psi_dev[i] with workspace ws[i] (tsq_set_potential must already have been
+ * called with that workspace) for steps[i] >= 0 steps.  All plans must have
+ * the same dtype and be periodic and of order 2 (else TSQ_ERR_UNSUPPORTED).
+ * `schedule` (NULL = defaults; segment_rows is ignored, the
+ * batch sizes its own tiles) applies to every problem.  The batch records the
+ * device pointers, which must stay valid while it is used; plans may be
+ * destroyed afterwards.  Errors: TSQ_ERR_ARG, TSQ_ERR_DTYPE (mixed dtypes),
+ * TSQ_ERR_STATE (a plan without potential or with another workspace),
+ * TSQ_ERR_DEVICE (device query failed). */
+int tsq_batch_create(tsq_plan* const* plans, void* const* psi_dev, void* const* ws,
+                     const int64_t* steps, int32_t n, const tsq_schedule* schedule,
+                     tsq_batch** out);
+int tsq_batch_destroy(tsq_batch* batch);
+
+/* Device bytes of the batch's work lists (job records and tiles of every
+ * launch), and the number of kernel launches and tiles one tsq_batch_launch
+ * makes.  Host only. */
+int tsq_batch_workspace_size(const tsq_batch* batch, size_t* bytes);
+int tsq_batch_info(const tsq_batch* batch, int64_t* launches, int64_t* tiles);
+
+/* Copy the work lists into `bws` (device, 256-byte aligned, at least
+ * tsq_batch_workspace_size bytes), asynchronously on `stream`.  Must precede
+ * tsq_batch_launch; `bws` must stay untouched while the batch is used.
+ * Errors: TSQ_ERR_ARG, TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
+int tsq_batch_upload(tsq_batch* batch, void* bws, size_t bws_bytes, void* stream);
+
+/* Enqueue every pass of every problem on `stream` (kernels and, for a
+ * problem whose pass count is odd and cannot be split, one device copy).
+ * With use_graph != 0 the sequence is captured into a HIP graph on the first
+ * call (stream must not be the null stream) and replayed by later calls.
+ * Each call advances every problem by its step count again.
+ * Errors: TSQ_ERR_STATE (not uploaded), TSQ_ERR_ARG, TSQ_ERR_DEVICE. */
+int tsq_batch_launch(tsq_batch* batch, int32_t use_graph, void* stream);
 
 #ifdef __cplusplus
 }

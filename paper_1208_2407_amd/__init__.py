@@ -29,7 +29,9 @@ BCS = {"periodic": 0, "closed": 1}
 
 EXPORTED = ("tsq_abi_version", "tsq_last_error", "tsq_plan_create", "tsq_plan_destroy",
             "tsq_workspace_size", "tsq_plan_set_schedule", "tsq_plan_get_schedule",
-            "tsq_evolve_passes", "tsq_set_potential", "tsq_evolve", "tsq_observables")
+            "tsq_evolve_passes", "tsq_set_potential", "tsq_evolve", "tsq_observables",
+            "tsq_batch_create", "tsq_batch_destroy", "tsq_batch_workspace_size", "tsq_batch_info",
+            "tsq_batch_upload", "tsq_batch_launch")
 
 
 class TsqError(RuntimeError):
@@ -53,7 +55,8 @@ class tsq_problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("mass", ctypes.c_double), ("hbar", ctypes.c_double),
-                ("dt", ctypes.c_double), ("bc", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+                ("dt", ctypes.c_double), ("bc", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
 
 
 _lib = None
@@ -82,6 +85,14 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.tsq_set_potential.argtypes = [vp, vp, vp, sz, vp]
     lib.tsq_evolve.argtypes = [vp, vp, i64, vp, sz, vp]
     lib.tsq_observables.argtypes = [vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d), vp, sz, vp]
+    vpp = ctypes.POINTER(vp)
+    lib.tsq_batch_create.argtypes = [vpp, vpp, vpp, ctypes.POINTER(i64), i32,
+                                     ctypes.POINTER(tsq_schedule), vpp]
+    lib.tsq_batch_destroy.argtypes = [vp]
+    lib.tsq_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.tsq_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.tsq_batch_upload.argtypes = [vp, vp, sz, vp]
+    lib.tsq_batch_launch.argtypes = [vp, i32, vp]
     for name in EXPORTED[2:]:
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
@@ -152,6 +163,41 @@ def tsq_observables(plan: int, psi_dev: int, V_dev: int, ws: int, ws_bytes: int,
     return n.value, e.value
 
 
+def tsq_batch_create(plans, psi_devs, wss, steps, schedule: Optional[tsq_schedule] = None) -> int:
+    n = len(plans)
+    arr = lambda xs: (ctypes.c_void_p * n)(*xs)
+    st = (ctypes.c_int64 * n)(*[int(v) for v in steps])
+    h = ctypes.c_void_p()
+    _check(load_library().tsq_batch_create(arr(plans), arr(psi_devs), arr(wss), st, n,
+                                           ctypes.byref(schedule) if schedule is not None else None,
+                                           ctypes.byref(h)))
+    return h.value
+
+
+def tsq_batch_destroy(batch: int) -> None:
+    _check(load_library().tsq_batch_destroy(batch))
+
+
+def tsq_batch_workspace_size(batch: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().tsq_batch_workspace_size(batch, ctypes.byref(n)))
+    return n.value
+
+
+def tsq_batch_info(batch: int) -> Tuple[int, int]:
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().tsq_batch_info(batch, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def tsq_batch_upload(batch: int, bws: int, nbytes: int, stream: int) -> None:
+    _check(load_library().tsq_batch_upload(batch, bws, nbytes, stream))
+
+
+def tsq_batch_launch(batch: int, use_graph: bool, stream: int) -> None:
+    _check(load_library().tsq_batch_launch(batch, 1 if use_graph else 0, stream))
+
+
 # ---------------------------------------------------------------- convenience layer
 
 def _torch():
@@ -173,9 +219,9 @@ class Plan:
     """
 
     def __init__(self, nx: int, ny: int, dt: float, dtype: str = "c128", *, dx=1.0, dy=1.0,
-                 mass=1.0, hbar=1.0, bc="periodic", device="cuda"):
+                 mass=1.0, hbar=1.0, bc="periodic", order: int = 2, device="cuda"):
         self.problem = tsq_problem(int(nx), int(ny), float(dx), float(dy), float(mass),
-                                   float(hbar), float(dt), BCS[bc], DTYPES[dtype])
+                                   float(hbar), float(dt), BCS[bc], DTYPES[dtype], int(order))
         self.dtype = dtype
         self.handle = tsq_plan_create(self.problem)
         self.device = device
@@ -249,6 +295,60 @@ class Plan:
                                ws.numel(), _stream_handle(psi.device))
 
 
+class Batch:
+    """Many independent problems advanced together (``tsq_batch_*``).
+
+    ``plans[i]`` (with its potential set) evolves ``psis[i]`` by ``steps[i]``;
+    all plans share one dtype.  :meth:`launch` enqueues every pass of every
+    problem on the current stream, optionally through a captured HIP graph
+    (replayed on later calls, on a side stream ordered with the current one).
+    """
+
+    def __init__(self, plans, psis, steps, schedule=(0, 0, 0, 0)):
+        torch = _torch()
+        if not (len(plans) == len(psis) == len(steps)) or not plans:
+            raise ValueError("plans, psis and steps must be non-empty and of equal length")
+        for pl, psi in zip(plans, psis):
+            pl._check_psi(psi)
+            if pl._ws is None:
+                raise ValueError("every plan needs set_potential() before batching")
+        self.plans, self.psis = list(plans), list(psis)
+        self.device = psis[0].device
+        sc = tsq_schedule(*[int(v) for v in schedule])
+        self.handle = tsq_batch_create([p.handle for p in plans], [t.data_ptr() for t in psis],
+                                       [p._ws.data_ptr() for p in plans], steps, sc)
+        self.bws = torch.empty(tsq_batch_workspace_size(self.handle), dtype=torch.uint8,
+                               device=self.device)
+        tsq_batch_upload(self.handle, self.bws.data_ptr(), self.bws.numel(),
+                         _stream_handle(self.device))
+        self._side = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                tsq_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def info(self) -> Tuple[int, int]:
+        """(kernel launches per call, tiles per call)."""
+        return tsq_batch_info(self.handle)
+
+    def launch(self, use_graph: bool = False) -> None:
+        torch = _torch()
+        if not use_graph:
+            tsq_batch_launch(self.handle, False, _stream_handle(self.device))
+            return
+        if self._side is None:
+            self._side = torch.cuda.Stream(device=self.device)
+        cur = torch.cuda.current_stream(self.device)
+        self._side.wait_stream(cur)
+        tsq_batch_launch(self.handle, True, self._side.cuda_stream)
+        cur.wait_stream(self._side)
+
+
 def _dtype_name(t) -> str:
     torch = _torch()
     if t.dtype == torch.complex128:
@@ -259,12 +359,13 @@ def _dtype_name(t) -> str:
 
 
 def evolve(psi, V, dt: float, steps: int, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
-           bc="periodic", steps_per_pass: int = 0, segment_rows: int = 0,
+           bc="periodic", order: int = 2, steps_per_pass: int = 0, segment_rows: int = 0,
            pairs_per_lane: int = 0, phase_store: int = 0):
-    """Evolve the device tensor psi (ny, nx) in place by `steps` second-order steps."""
+    """Evolve the device tensor psi (ny, nx) in place by `steps` steps of U2 (order 2)
+    or U4 (order 4)."""
     ny, nx = psi.shape
     plan = Plan(nx, ny, dt, _dtype_name(psi), dx=dx, dy=dy, mass=mass, hbar=hbar, bc=bc,
-                device=psi.device)
+                order=order, device=psi.device)
     plan.set_schedule(steps_per_pass, segment_rows, pairs_per_lane, phase_store)
     plan.set_potential(V)
     plan.evolve(psi, steps)

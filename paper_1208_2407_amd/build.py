@@ -4,6 +4,8 @@ Usage: python -m paper_1208_2407_amd.build
 """
 from __future__ import annotations
 
+import concurrent.futures
+import glob
 import os
 import shutil
 import subprocess
@@ -35,17 +37,28 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libtsq)")
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every csrc/*.hip (device) and csrc/*.cpp (host) file in parallel and
+    link libtsq.so."""
     os.makedirs(OUT_DIR, exist_ok=True)
     cc = hipcc()
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
+    cmds = []
     objs = []
-    for src, dev in (("tsq_kernels.hip", True), ("tsq_host.cpp", False)):
-        obj = os.path.join(OUT_DIR, src + ".o")
-        cmd = [cc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + (DEVICE if dev else [])
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+    for src in srcs:
+        obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
+        dev = src.endswith(".hip")
+        cmds.append([cc, "-c", src, "-o", obj] + COMMON + (DEVICE if dev else []))
         objs.append(obj)
+    if verbose:
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    jobs = jobs or min(len(cmds), os.cpu_count() or 1, 8)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        for r in ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds):
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError(f"hipcc failed: {' '.join(r.args)}")
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:

@@ -1,0 +1,10 @@
+// March kernel instances: complex64, closed variant.
+#include "tsq_march.hpp"
+
+namespace tsq {
+
+const void* march_ptr_c64_closed(int steps, bool last, int ppl, bool lds) {
+    return pick_kernel<C64>(steps, last, ppl, lds, Variant::Closed);
+}
+
+}  // namespace tsq

@@ -12,15 +12,28 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <algorithm>
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "../../include/tsq.h"
 #include "tsq_internal.h"
 
+// One kind of second-order sub-step: its duration, rotation coefficients and
+// phase table.  Order 2 has one kind (dt); order 4 has two (p dt, (1-4p) dt).
+struct SubStep {
+    double dt;
+    tsq::Coef64 oxh, oyh, ox2, oy2;  // tau = dt/2 and tau = dt along x, y
+    size_t off_ptab;
+};
+
 struct tsq_plan {
     tsq_problem p;
     double Jx, Jy, eps0;
-    tsq::Coef64 oxh, oyh, ox2, oy2;
+    tsq::Coef64 oxh, oyh, ox2, oy2;   // of kind 0
+    int nkinds;
+    SubStep kind[2];
     tsq_schedule sched;   // resolved (segment_rows may stay 0 = per launch)
     size_t sites, elem, pelem;
     size_t off_psi2, off_ptab, off_scratch, ws_bytes;
@@ -97,26 +110,28 @@ int device_cus() {
     return g_dev.cus;
 }
 
-int occupancy_cached(int dtype, int steps, bool last, int ppl, bool lds) {
-    // [dtype][steps][last][ppl][lds]; 0 = not yet queried
-    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3][2];
-    std::atomic<int>& slot = table[dtype & 1][steps][last ? 1 : 0][ppl][lds ? 1 : 0];
+int occupancy_cached(int dtype, int steps, bool last, int ppl, bool lds, bool closed) {
+    // [dtype][steps][last][ppl][lds][closed]; 0 = not yet queried
+    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3][2][2];
+    std::atomic<int>& slot =
+        table[dtype & 1][steps][last ? 1 : 0][ppl][lds ? 1 : 0][closed ? 1 : 0];
     int v = slot.load(std::memory_order_relaxed);
     if (v == 0) {
-        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl, lds);
+        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl, lds, false, closed);
         if (v <= 0) v = 1;
         slot.store(v, std::memory_order_relaxed);
     }
     return v;
 }
 
-int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl, bool lds) {
+int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl, bool lds, bool closed) {
     const tsq::MarchGeometry g = tsq::march_geometry(p->p.nx, p->p.ny, steps, last, ppl, 2);
     int cus = device_cus();
     if (cus <= 0) cus = 256;
     const long long slots =
-        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl, lds) * tsq::kWavesPerBlock;
-    const long long pairs = p->p.ny / 2;
+        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl, lds, closed) *
+        tsq::kWavesPerBlock;
+    const long long pairs = (p->p.ny + 1) / 2;
     long long segs = slots / g.nstrips;
     if (segs < 1) segs = 1;
     if (segs > pairs) segs = pairs;
@@ -158,6 +173,55 @@ bool pass_runs(int64_t steps, int S, std::vector<Run>& runs) {
     return true;
 }
 
+// Passes of one evolution as groups of equal passes.  A group's passes all
+// apply `size` sub-steps of one kind; `opens` marks that its first pass starts
+// a run of that kind (opening odd factor of half length), `closes` that its
+// last pass ends the run (closing odd factor).  Order 2 is one run of `steps`
+// sub-steps; order 4 is U2(p)^2 U2(m) U2(p)^2 per step, so runs alternate
+// between 2 or 4 p sub-steps (neighbouring steps share theirs) and 1 m sub-step.
+struct PassGroup {
+    int kind;
+    int size;
+    int64_t count;
+    bool opens, closes;
+};
+
+bool pass_groups(const tsq_plan* p, int64_t steps, int S, std::vector<PassGroup>& g) {
+    g.clear();
+    auto add_run = [&](int kind, int64_t count) {
+        const int64_t full = count / S;
+        const int rem = (int)(count % S);
+        if (full > 0) g.push_back(PassGroup{kind, S, full, true, rem == 0});
+        if (rem > 0) g.push_back(PassGroup{kind, rem, 1, full == 0, true});
+    };
+    if (steps <= 0) return false;
+    if (p->p.order == 4) {
+        add_run(0, 2);
+        for (int64_t i = 0; i < steps; ++i) {
+            add_run(1, 1);
+            add_run(0, i + 1 < steps ? 4 : 2);
+        }
+    } else {
+        add_run(0, steps);
+    }
+    int64_t total = 0;
+    for (const PassGroup& x : g) total += x.count;
+    if (!(total & 1)) return false;
+    for (size_t i = g.size(); i-- > 0;) {
+        if (g[i].size < 2) continue;
+        const PassGroup o = g[i];
+        const int a = o.size / 2, b = o.size - a;
+        std::vector<PassGroup> tail(g.begin() + i + 1, g.end());
+        g.resize(i);
+        if (o.count > 1) g.push_back(PassGroup{o.kind, o.size, o.count - 1, o.opens, false});
+        g.push_back(PassGroup{o.kind, a, 1, o.count > 1 ? false : o.opens, false});
+        g.push_back(PassGroup{o.kind, b, 1, false, o.closes});
+        g.insert(g.end(), tail.begin(), tail.end());
+        return false;
+    }
+    return true;
+}
+
 int64_t run_passes(const std::vector<Run>& runs) {
     int64_t n = 0;
     for (const Run& r : runs) n += r.count;
@@ -180,6 +244,275 @@ extern "C" {
 
 int tsq_abi_version(void) { return TSQ_ABI_VERSION; }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- batched form (host side)
+
+struct BatchLaunch {
+    int steps;
+    bool last;
+    size_t jobs_off;
+    int njobs;
+    size_t tiles_off;
+    int ntiles;
+    int nwaves;
+};
+
+struct BatchCopy {
+    void* dst;
+    const void* src;
+    size_t bytes;
+};
+
+struct tsq_batch {
+    int dtype = 0;
+    tsq_schedule sched{};
+    std::vector<BatchLaunch> launches;
+    std::vector<BatchCopy> copies;
+    std::vector<unsigned char> blob;  // host image of the device work lists
+    char* bws = nullptr;              // device copy (after upload)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t total_tiles = 0;
+};
+
+namespace {
+
+size_t blob_reserve(std::vector<unsigned char>& blob, size_t bytes) {
+    const size_t off = align_up(blob.size(), 256);
+    blob.resize(off + bytes);
+    return off;
+}
+
+template <class R>
+void append_launch(tsq_batch* b, int steps, bool last, const std::vector<tsq::PassDesc>& descs,
+                   int slots) {
+    const int ppl = b->sched.pairs_per_lane;
+    const int K = steps + (last ? 1 : 0);
+    // Tile height: the strips of all problems stacked, cut into about one tile
+    // per resident wavefront, never shorter than 2K row pairs.
+    long long strip_rows = 0;
+    for (const tsq::PassDesc& d : descs)
+        strip_rows += (long long)tsq::march_geometry(d.nx, d.ny, steps, last, ppl, 2).nstrips * d.ny;
+    long long h = (strip_rows + slots - 1) / slots;
+    if (h < 4LL * K) h = 4LL * K;
+    h = (h + 1) & ~1LL;
+
+    std::vector<tsq::MarchArgs<R>> jobs;
+    std::vector<tsq::BatchTile> tiles;
+    for (size_t j = 0; j < descs.size(); ++j) {
+        tsq::PassDesc d = descs[j];
+        d.seg_rows = (int)std::min<long long>(h, d.ny);
+        const tsq::MarchGeometry g = tsq::march_geometry(d.nx, d.ny, steps, last, ppl, d.seg_rows);
+        jobs.push_back(tsq::make_march_args<R>(d, g));
+        for (int st = 0; st < g.nstrips; ++st)
+            for (int sg = 0; sg < g.nsegs; ++sg) {
+                const int rows = std::min(d.seg_rows, d.ny - sg * d.seg_rows);
+                tiles.push_back(tsq::BatchTile{(int)j, st, sg, rows});
+            }
+    }
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const tsq::BatchTile& x, const tsq::BatchTile& y) { return x.rows > y.rows; });
+    BatchLaunch L;
+    L.steps = steps;
+    L.last = last;
+    L.njobs = (int)jobs.size();
+    L.ntiles = (int)tiles.size();
+    L.nwaves = std::min(L.ntiles, slots);
+    L.jobs_off = blob_reserve(b->blob, jobs.size() * sizeof(tsq::MarchArgs<R>));
+    std::memcpy(b->blob.data() + L.jobs_off, jobs.data(), jobs.size() * sizeof(tsq::MarchArgs<R>));
+    L.tiles_off = blob_reserve(b->blob, tiles.size() * sizeof(tsq::BatchTile));
+    std::memcpy(b->blob.data() + L.tiles_off, tiles.data(), tiles.size() * sizeof(tsq::BatchTile));
+    b->launches.push_back(L);
+    b->total_tiles += L.ntiles;
+}
+
+int enqueue_batch(tsq_batch* b, hipStream_t s) {
+    const bool lds = b->sched.phase_store == 2;
+    for (const BatchLaunch& L : b->launches) {
+        hipError_t e = tsq::launch_batch(b->dtype, L.steps, L.last, b->sched.pairs_per_lane, lds,
+                                         b->bws + L.jobs_off,
+                                         reinterpret_cast<const tsq::BatchTile*>(b->bws + L.tiles_off),
+                                         L.ntiles, L.nwaves, s);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "batched pass launch: %s", hipGetErrorString(e));
+    }
+    for (const BatchCopy& c : b->copies) {
+        hipError_t e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "batch copy back: %s", hipGetErrorString(e));
+    }
+    return TSQ_OK;
+}
+
+void drop_graph(tsq_batch* b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsq_batch_create(tsq_plan* const* plans, void* const* psi, void* const* ws, const int64_t* steps,
+                     int32_t n, const tsq_schedule* schedule, tsq_batch** out) {
+    if (!plans || !psi || !ws || !steps || !out || n < 1)
+        return fail(TSQ_ERR_ARG, "null argument or empty batch");
+    const int dtype = plans[0] ? plans[0]->p.dtype : -1;
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i] || !psi[i] || !ws[i]) return fail(TSQ_ERR_ARG, "null entry %d", i);
+        if (steps[i] < 0) return fail(TSQ_ERR_ARG, "steps[%d] = %lld < 0", i, (long long)steps[i]);
+        if (plans[i]->p.dtype != dtype) return fail(TSQ_ERR_DTYPE, "batch mixes dtypes (entry %d)", i);
+        if (plans[i]->p.order != 2 || plans[i]->p.bc != TSQ_BC_PERIODIC)
+            return fail(TSQ_ERR_UNSUPPORTED,
+                        "entry %d: the batched form runs periodic order-2 plans only", i);
+        if (plans[i]->ws_bound != ws[i])
+            return fail(TSQ_ERR_STATE, "entry %d: workspace is not the one given to tsq_set_potential", i);
+        if (reinterpret_cast<uintptr_t>(psi[i]) % 16 != 0)
+            return fail(TSQ_ERR_ARG, "entry %d: psi must be 16-byte aligned", i);
+    }
+    tsq_schedule want = schedule ? *schedule : tsq_schedule{0, 0, 0, 0};
+    want.segment_rows = 0;
+    tsq_schedule sc;
+    if (want.steps_per_pass < 0 || want.steps_per_pass > tsq::kMaxSteps || want.pairs_per_lane < 0 ||
+        want.pairs_per_lane > 2 || want.phase_store < 0 || want.phase_store > 2 ||
+        !resolve_schedule(want, sc))
+        return fail(TSQ_ERR_ARG, "invalid batch schedule");
+    int cus = device_cus();
+    if (cus <= 0) return fail(TSQ_ERR_DEVICE, "no device to size the batch for");
+
+    // passes of every problem
+    std::vector<std::vector<int>> sizes(n);
+    int64_t maxp = 0, total = 0;
+    tsq_batch* b = new (std::nothrow) tsq_batch();
+    if (!b) return fail(TSQ_ERR_ARG, "out of host memory");
+    b->dtype = dtype;
+    b->sched = sc;
+    for (int i = 0; i < n; ++i) {
+        std::vector<Run> runs;
+        const bool cb = steps[i] > 0 && pass_runs(steps[i], sc.steps_per_pass, runs);
+        total += run_passes(runs);
+        if (total > 50000000LL) {
+            delete b;
+            return fail(TSQ_ERR_ARG, "batch of %lld passes is too large", (long long)total);
+        }
+        for (const Run& r : runs)
+            for (int64_t k = 0; k < r.count; ++k) sizes[i].push_back(r.size);
+        maxp = std::max<int64_t>(maxp, (int64_t)sizes[i].size());
+        if (cb) {
+            char* w = static_cast<char*>(ws[i]);
+            b->copies.push_back(BatchCopy{psi[i], w + plans[i]->off_psi2, plans[i]->sites * plans[i]->elem});
+        }
+    }
+    const bool lds = sc.phase_store == 2;
+    for (int64_t l = 0; l < maxp; ++l) {
+        std::map<std::pair<int, bool>, std::vector<tsq::PassDesc>> groups;
+        for (int i = 0; i < n; ++i) {
+            if ((int64_t)sizes[i].size() <= l) continue;
+            const tsq_plan* pl = plans[i];
+            char* w = static_cast<char*>(ws[i]);
+            void* buf[2] = {psi[i], w + pl->off_psi2};
+            tsq::PassDesc d;
+            d.src = buf[l & 1];
+            d.dst = buf[(l + 1) & 1];
+            d.ptab = w + pl->off_ptab;
+            d.nx = pl->p.nx;
+            d.ny = pl->p.ny;
+            d.steps = sizes[i][l];
+            d.first = (l == 0);
+            d.last = (l + 1 == (int64_t)sizes[i].size());
+            d.seg_rows = 2;
+            d.pairs_per_lane = sc.pairs_per_lane;
+            d.phase_lds = lds;
+            d.oxh = pl->oxh;
+            d.oyh = pl->oyh;
+            d.ox2 = pl->ox2;
+            d.oy2 = pl->oy2;
+            groups[{d.steps, d.last}].push_back(d);
+        }
+        for (auto& kv : groups) {
+            const int st = kv.first.first;
+            const bool last = kv.first.second;
+            int bpc = tsq::march_blocks_per_cu(dtype, st, last, sc.pairs_per_lane, lds, true);
+            if (bpc <= 0) bpc = 1;
+            const int slots = cus * bpc * tsq::kWavesPerBlock;
+            if (dtype == TSQ_C128)
+                append_launch<double>(b, st, last, kv.second, slots);
+            else
+                append_launch<float>(b, st, last, kv.second, slots);
+        }
+    }
+    *out = b;
+    return ok();
+}
+
+int tsq_batch_destroy(tsq_batch* b) {
+    if (b) drop_graph(b);
+    delete b;
+    return ok();
+}
+
+int tsq_batch_workspace_size(const tsq_batch* b, size_t* bytes) {
+    if (!b || !bytes) return fail(TSQ_ERR_ARG, "null argument");
+    *bytes = align_up(b->blob.size(), 256) + 256;
+    return ok();
+}
+
+int tsq_batch_info(const tsq_batch* b, int64_t* launches, int64_t* tiles) {
+    if (!b || !launches || !tiles) return fail(TSQ_ERR_ARG, "null argument");
+    *launches = (int64_t)b->launches.size();
+    *tiles = b->total_tiles;
+    return ok();
+}
+
+int tsq_batch_upload(tsq_batch* b, void* bws, size_t bytes, void* stream) {
+    if (!b || !bws) return fail(TSQ_ERR_ARG, "null argument");
+    if (reinterpret_cast<uintptr_t>(bws) % 256 != 0)
+        return fail(TSQ_ERR_WORKSPACE, "batch workspace must be 256-byte aligned");
+    size_t need = 0;
+    tsq_batch_workspace_size(b, &need);
+    if (bytes < need)
+        return fail(TSQ_ERR_WORKSPACE, "batch workspace of %zu bytes is smaller than %zu", bytes, need);
+    if (b->bws != bws) drop_graph(b);
+    hipError_t e = hipMemcpyAsync(bws, b->blob.data(), b->blob.size(), hipMemcpyHostToDevice,
+                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "batch upload: %s", hipGetErrorString(e));
+    b->bws = static_cast<char*>(bws);
+    return ok();
+}
+
+int tsq_batch_launch(tsq_batch* b, int32_t use_graph, void* stream) {
+    if (!b) return fail(TSQ_ERR_ARG, "null batch");
+    if (!b->bws) return fail(TSQ_ERR_STATE, "tsq_batch_upload has not been called");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!use_graph) {
+        int rc = enqueue_batch(b, s);
+        return rc ? rc : ok();
+    }
+    if (s == nullptr) return fail(TSQ_ERR_ARG, "graph capture needs a non-null stream");
+    if (!b->exec) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "begin capture: %s", hipGetErrorString(e));
+        int rc = enqueue_batch(b, s);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s, &g);
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e2 != hipSuccess) return fail(TSQ_ERR_DEVICE, "end capture: %s", hipGetErrorString(e2));
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(b);
+            return fail(TSQ_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        }
+    }
+    hipError_t e = hipGraphLaunch(b->exec, s);
+    if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "graph launch: %s", hipGetErrorString(e));
+    return ok();
+}
+
 const char* tsq_last_error(void) { return g_err.c_str(); }
 
 int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
@@ -201,8 +534,8 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
     if (!std::isfinite(pr->dt)) return fail(TSQ_ERR_ARG, "dt must be finite (%g)", pr->dt);
     if (pr->dtype != TSQ_C64 && pr->dtype != TSQ_C128)
         return fail(TSQ_ERR_DTYPE, "unknown dtype %d", pr->dtype);
-    if (pr->bc == TSQ_BC_CLOSED)
-        return fail(TSQ_ERR_UNSUPPORTED, "closed boundaries are not implemented in this build");
+    if (pr->order != 0 && pr->order != 2 && pr->order != 4)
+        return fail(TSQ_ERR_ARG, "order must be 2 or 4 (got %d)", pr->order);
 
     tsq_plan* p = new (std::nothrow) tsq_plan();
     if (!p) return fail(TSQ_ERR_ARG, "out of host memory");
@@ -211,18 +544,39 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
     p->Jx = hb * hb / (2.0 * m * pr->dx * pr->dx);
     p->Jy = hb * hb / (2.0 * m * pr->dy * pr->dy);
     p->eps0 = hb * hb / (m * pr->dx * pr->dx) + hb * hb / (m * pr->dy * pr->dy);
-    const double h = 0.5 * pr->dt;
-    p->oxh = block_coef(h, p->Jx, hb);
-    p->oyh = block_coef(h, p->Jy, hb);
-    p->ox2 = block_coef(pr->dt, p->Jx, hb);
-    p->oy2 = block_coef(pr->dt, p->Jy, hb);
+    if (p->p.order == 0) p->p.order = 2;
+    double dts[2] = {pr->dt, 0.0};
+    p->nkinds = 1;
+    if (p->p.order == 4) {
+        const double q = 1.0 / (4.0 - std::cbrt(4.0));
+        dts[0] = q * pr->dt;
+        dts[1] = (1.0 - 4.0 * q) * pr->dt;
+        p->nkinds = 2;
+    }
+    for (int k = 0; k < p->nkinds; ++k) {
+        SubStep& u = p->kind[k];
+        u.dt = dts[k];
+        u.oxh = block_coef(0.5 * dts[k], p->Jx, hb);
+        u.oyh = block_coef(0.5 * dts[k], p->Jy, hb);
+        u.ox2 = block_coef(dts[k], p->Jx, hb);
+        u.oy2 = block_coef(dts[k], p->Jy, hb);
+    }
+    p->oxh = p->kind[0].oxh;
+    p->oyh = p->kind[0].oyh;
+    p->ox2 = p->kind[0].ox2;
+    p->oy2 = p->kind[0].oy2;
     resolve_schedule(tsq_schedule{0, 0, 0, 0}, p->sched);
     p->sites = (size_t)pr->nx * (size_t)pr->ny;
     p->elem = pr->dtype == TSQ_C128 ? 16 : 8;
     p->pelem = 16;  // complex128: exp(-i phi); complex64: hi + lo complex floats
     p->off_psi2 = 0;
     p->off_ptab = align_up(p->sites * p->elem, 256);
-    p->off_scratch = align_up(p->off_ptab + p->sites * p->pelem, 256);
+    size_t end = p->off_ptab;
+    for (int k = 0; k < p->nkinds; ++k) {
+        p->kind[k].off_ptab = end;
+        end = align_up(end + p->sites * p->pelem, 256);
+    }
+    p->off_scratch = end;
     p->ws_bytes = p->off_scratch + kScratchBytes;
     p->ws_bound = nullptr;
     *out = p;
@@ -257,6 +611,8 @@ int tsq_plan_set_schedule(tsq_plan* plan, const tsq_schedule* sc) {
                     "no kernel for steps_per_pass %d, pairs_per_lane %d, phase_store %d "
                     "(registers hold at most %d steps; LDS needs 1 pair per lane)",
                     r.steps_per_pass, r.pairs_per_lane, r.phase_store, tsq::kMaxRegSteps);
+    if (plan->p.bc == TSQ_BC_CLOSED && r.pairs_per_lane != 1)
+        return fail(TSQ_ERR_ARG, "closed meshes run with 1 pair per lane");
     plan->sched = r;
     return ok();
 }
@@ -270,9 +626,14 @@ int tsq_plan_get_schedule(const tsq_plan* plan, tsq_schedule* sc) {
 int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int32_t* copy_back) {
     if (!plan || !passes || !copy_back) return fail(TSQ_ERR_ARG, "null argument");
     if (steps < 0) return fail(TSQ_ERR_ARG, "steps must be >= 0 (%lld)", (long long)steps);
-    std::vector<Run> runs;
-    const bool cb = steps > 0 && pass_runs(steps, plan->sched.steps_per_pass, runs);
-    *passes = run_passes(runs);
+    if (plan->p.order == 4 && steps > 10000000LL)
+        return fail(TSQ_ERR_ARG, "order-4 evolution of %lld steps is too long for one call",
+                    (long long)steps);
+    std::vector<PassGroup> groups;
+    const bool cb = pass_groups(plan, steps, plan->sched.steps_per_pass, groups);
+    int64_t n = 0;
+    for (const PassGroup& x : groups) n += x.count;
+    *passes = n;
     *copy_back = cb ? 1 : 0;
     return ok();
 }
@@ -282,10 +643,14 @@ int tsq_set_potential(tsq_plan* plan, const double* V, void* ws, size_t ws_bytes
     int rc = check_ws(plan, ws, ws_bytes);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
-    hipError_t e = tsq::launch_phase_table(plan->p.dtype, V, w + plan->off_ptab,
-                                           (long long)plan->sites, plan->p.dt, plan->eps0,
-                                           plan->p.hbar, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "phase table launch: %s", hipGetErrorString(e));
+    for (int k = 0; k < plan->nkinds; ++k) {
+        hipError_t e = tsq::launch_phase_table(plan->p.dtype, V, w + plan->kind[k].off_ptab,
+                                               (long long)plan->sites, plan->kind[k].dt,
+                                               plan->eps0, plan->p.hbar,
+                                               static_cast<hipStream_t>(stream));
+        if (e != hipSuccess)
+            return fail(TSQ_ERR_DEVICE, "phase table launch: %s", hipGetErrorString(e));
+    }
     plan->ws_bound = ws;
     return ok();
 }
@@ -308,31 +673,35 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
     const int ppl = plan->sched.pairs_per_lane;
     const bool lds = plan->sched.phase_store == 2;
 
-    std::vector<Run> runs;
-    const bool copy_back = pass_runs(steps, S, runs);
-    const int64_t npasses = run_passes(runs);
+    if (plan->p.order == 4 && steps > 10000000LL)
+        return fail(TSQ_ERR_ARG, "order-4 evolution of %lld steps is too long for one call",
+                    (long long)steps);
+    std::vector<PassGroup> groups;
+    const bool copy_back = pass_groups(plan, steps, S, groups);
 
     tsq::PassDesc d;
-    d.ptab = w + plan->off_ptab;
     d.nx = plan->p.nx;
     d.ny = plan->p.ny;
     d.pairs_per_lane = ppl;
     d.phase_lds = lds;
-    d.oxh = plan->oxh;
-    d.oyh = plan->oyh;
-    d.ox2 = plan->ox2;
-    d.oy2 = plan->oy2;
+    d.closed = plan->p.bc == TSQ_BC_CLOSED;
     int64_t i = 0;
-    for (const Run& r : runs) {
-        for (int64_t k = 0; k < r.count; ++k, ++i) {
+    for (const PassGroup& g : groups) {
+        const SubStep& u = plan->kind[g.kind];
+        d.ptab = w + u.off_ptab;
+        d.oxh = u.oxh;
+        d.oyh = u.oyh;
+        d.ox2 = u.ox2;
+        d.oy2 = u.oy2;
+        for (int64_t k = 0; k < g.count; ++k, ++i) {
             d.src = buf[i & 1];
             d.dst = buf[(i + 1) & 1];
-            d.steps = r.size;
-            d.first = (i == 0);
-            d.last = (i + 1 == npasses);
+            d.steps = g.size;
+            d.first = g.opens && k == 0;
+            d.last = g.closes && k + 1 == g.count;
             d.seg_rows = plan->sched.segment_rows
                              ? plan->sched.segment_rows
-                             : default_seg_rows(plan, d.steps, d.last, ppl, lds);
+                             : default_seg_rows(plan, d.steps, d.last, ppl, lds, d.closed);
             hipError_t e = tsq::launch_pass(plan->p.dtype, d, s);
             if (e != hipSuccess)
                 return fail(TSQ_ERR_DEVICE, "step pass launch: %s", hipGetErrorString(e));
@@ -355,7 +724,8 @@ int tsq_observables(const tsq_plan* plan, const void* psi, const double* V, doub
     double* result = scratch + 2 * tsq::kReduceBlocks;
     const int nblocks = plan->p.ny < tsq::kReduceBlocks ? plan->p.ny : tsq::kReduceBlocks;
     hipError_t e = tsq::launch_observables(plan->p.dtype, psi, V, plan->p.nx, plan->p.ny, plan->Jx,
-                                           plan->Jy, plan->eps0, scratch, nblocks, result, s);
+                                           plan->Jy, plan->eps0, plan->p.bc == TSQ_BC_CLOSED,
+                                           scratch, nblocks, result, s);
     if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "observables launch: %s", hipGetErrorString(e));
     double host[2];
     e = hipMemcpyAsync(host, result, sizeof host, hipMemcpyDeviceToHost, s);

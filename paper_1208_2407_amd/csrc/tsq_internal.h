@@ -25,6 +25,7 @@ struct PassDesc {
     int seg_rows;         // rows per wavefront segment (even)
     int pairs_per_lane;   // 1 or 2 x-pairs held by each lane
     bool phase_lds;       // phase ring in LDS (else registers)
+    bool closed = false;  // hard walls instead of periodic wrap
     Coef64 oxh, oyh;      // tau = dt/2 along x, y
     Coef64 ox2, oy2;      // tau = dt along x, y
 };
@@ -45,17 +46,66 @@ struct MarchGeometry {
 MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per_lane,
                              int seg_rows);
 
+// Kernel arguments of one pass over one problem (also the job record of the
+// batched kernel, uploaded to device memory).  R = double (complex128) or
+// float (complex64).
+template <class R>
+struct MarchArgs {
+    const void* src;
+    void* dst;
+    const void* ptab;
+    int nx, ny, strip_sites, seg_rows, nstrips, nsegs;
+    R o1xs, o1xd, o1ys, o1yd;  // odd factors opening the pass: tau = dt/2 (first pass) or dt
+    R o2xs, o2xd, o2ys, o2yd;  // odd factors between steps, tau = dt
+    R ehxs, ehxd, ehys, ehyd;  // even factors and the closing odd factors, tau = dt/2
+};
+
+template <class R>
+MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
+    MarchArgs<R> a;
+    a.src = d.src;
+    a.dst = d.dst;
+    a.ptab = d.ptab;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.strip_sites = g.strip_sites;
+    a.seg_rows = d.seg_rows;
+    a.nstrips = g.nstrips;
+    a.nsegs = g.nsegs;
+    const Coef64& ox1 = d.first ? d.oxh : d.ox2;
+    const Coef64& oy1 = d.first ? d.oyh : d.oy2;
+    a.o1xs = (R)ox1.s; a.o1xd = (R)ox1.d; a.o1ys = (R)oy1.s; a.o1yd = (R)oy1.d;
+    a.o2xs = (R)d.ox2.s; a.o2xd = (R)d.ox2.d; a.o2ys = (R)d.oy2.s; a.o2yd = (R)d.oy2.d;
+    a.ehxs = (R)d.oxh.s; a.ehxd = (R)d.oxh.d; a.ehys = (R)d.oyh.s; a.ehyd = (R)d.oyh.d;
+    return a;
+}
+
+// One entry of the batched kernel's work list.
+struct BatchTile {
+    int job;    // index into the launch's MarchArgs array
+    int strip;
+    int seg;
+    int rows;   // rows the tile marches (host-side sort key)
+};
+
 // Resident blocks per compute unit of one march kernel instance (0 if the
 // query fails); used to size segments so a pass is one round of resident waves.
-int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds);
-bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds);
+int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
+                        bool batch = false, bool closed = false);
+bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
+                          bool closed = false);
 
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long sites,
                               double dt, double eps0, double hbar, hipStream_t s);
 hipError_t launch_pass(int dtype, const PassDesc& d, hipStream_t s);
+// Batched pass: `nwaves` wavefronts walk `ntiles` tiles of `jobs` (device
+// MarchArgs<double> for complex128, MarchArgs<float> for complex64).
+hipError_t launch_batch(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
+                        const void* jobs, const BatchTile* tiles, int ntiles, int nwaves,
+                        hipStream_t s);
 hipError_t launch_observables(int dtype, const void* psi, const double* V, int nx, int ny,
-                              double Jx, double Jy, double eps0, double* partial,
+                              double Jx, double Jy, double eps0, bool closed, double* partial,
                               int nblocks, double* result, hipStream_t s);
 
 constexpr int kReduceBlocks = 1024;

@@ -1,0 +1,634 @@
+// Kernel templates of the fused step march of the second-order
+// Trotter-Suzuki step for gfx950 (Wittek & Cucchietti, Sec. 2), instantiated
+// per dtype and variant in march_<dtype>_<variant>.hip.
+//
+// Fused step march (one launch = `S` time steps over the whole mesh):
+//   * Each wavefront owns a strip of the mesh: 64 lanes across x, each lane
+//     holding PPL consecutive even x-pairs (2j, 2j+1) of one row in registers,
+//     and it marches down y over a segment of rows.
+//   * Even x-pairs are rotated inside a lane; odd x-pairs (2j+1, 2j+2) that
+//     straddle two lanes swap the partner value with a DPP wavefront shift
+//     (no LDS, no barrier).
+//   * y-pairs are rows held by the same lane: the even pair (2q, 2q+1) is a
+//     row pair, the odd pair (2q+1, 2q+2) joins a row pair to the next one.
+//   * The S steps form a register pipeline: stage k works on the row pair k
+//     behind the one just loaded, so a row pair leaves the last stage S
+//     steps older, having been read and written in device memory once.
+//   * Lanes at the strip edges and row pairs at the segment ends are a halo
+//     whose results are discarded: the dependence of one step reaches one
+//     pair along each axis, so S steps need S pairs of halo (plus one for the
+//     closing odd factor of the last pass).
+// Operation order of one evolution of N steps, h = dt/2 (left applied first):
+//   Ox(h) Oy(h) [Ex Ey P Ey Ex](h) { Ox(2h) Oy(2h) [Ex Ey P Ey Ex](h) }^(N-1) Ox(h) Oy(h)
+// which equals U2(dt)^N of Sec. 2 exactly in real arithmetic (x and y
+// factors commute; two consecutive Ox(h) are one Ox(2h)).  Every site goes
+// through the same operations in the same order whatever the strip, segment
+// and S, so results are bitwise independent of the schedule.
+
+#pragma once
+
+#include <utility>
+
+#include "tsq_internal.h"
+
+namespace tsq {
+namespace {
+
+// ------------------------------------------------------------------ scalars
+
+__device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// DPP wavefront shifts: lane i receives lane i-1 (from_left) or i+1 (from_right).
+// Lanes without a source receive 0; they lie in the discarded halo.
+__device__ __forceinline__ int dpp_from_left(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int dpp_from_right(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v) {
+    return __hiloint2double(dpp_from_left(__double2hiint(v)), dpp_from_left(__double2loint(v)));
+}
+__device__ __forceinline__ double from_right(double v) {
+    return __hiloint2double(dpp_from_right(__double2hiint(v)), dpp_from_right(__double2loint(v)));
+}
+
+// One site of a 2x2 block exponential [[c, i s], [i s, c]] with its partner b:
+//   a <- a + (i s b - d a),   d = 1 - c.
+template <class R>
+__device__ __forceinline__ void rot_site(R& ar, R& ai, R br, R bi, R s, R d) {
+    R nr = mad(-d, ar, mad(-s, bi, ar));
+    R ni = mad(-d, ai, mad(s, br, ai));
+    ar = nr;
+    ai = ni;
+}
+
+template <class R>
+__device__ __forceinline__ void rot_pair(R& ar, R& ai, R& br, R& bi, R s, R d) {
+    R a0 = ar, a1 = ai;
+    rot_site(ar, ai, br, bi, s, d);
+    rot_site(br, bi, a0, a1, s, d);
+}
+
+// Potential phase, complex128: psi <- psi * p, p = exp(-i phi) in FP64.
+__device__ __forceinline__ void apply_phase(double& re, double& im, const double2 p) {
+    double t = im * p.y;
+    double nr = mad(re, p.x, -t);
+    double ni = mad(re, p.y, im * p.x);
+    re = nr;
+    im = ni;
+}
+
+// Potential phase, complex64: p = (hi.re, hi.im, lo.re, lo.im) with
+// exp(-i phi) = hi + lo to ~48 bits; the lo product is formed first so the
+// table contributes no coherent per-site error step after step.
+__device__ __forceinline__ void apply_phase(float& re, float& im, const float4 p) {
+    float tr = mad(re, p.z, -(im * p.w));
+    float ti = mad(re, p.w, im * p.z);
+    float nr = mad(re, p.x, mad(-im, p.y, tr));
+    float ni = mad(re, p.y, mad(im, p.x, ti));
+    re = nr;
+    im = ni;
+}
+
+// ------------------------------------------------------------------ dtype traits
+
+struct C128 {
+    using R = double;
+    using PT = double2;
+};
+struct C64 {
+    using R = float;
+    using PT = float4;
+};
+
+template <class R, int SPL>
+struct Row {
+    R re[SPL];
+    R im[SPL];
+};
+
+// Load / store one x-pair (2 sites starting at even column `x`) of row `r`.
+template <int SPL>
+__device__ __forceinline__ void load_pair(const void* base, long long off, Row<double, SPL>& row, int p) {
+    const double2* q = reinterpret_cast<const double2*>(base) + off;
+    double2 a = q[0], b = q[1];
+    row.re[2 * p] = a.x; row.im[2 * p] = a.y;
+    row.re[2 * p + 1] = b.x; row.im[2 * p + 1] = b.y;
+}
+template <int SPL>
+__device__ __forceinline__ void load_pair(const void* base, long long off, Row<float, SPL>& row, int p) {
+    const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(base) + off);
+    row.re[2 * p] = a.x; row.im[2 * p] = a.y;
+    row.re[2 * p + 1] = a.z; row.im[2 * p + 1] = a.w;
+}
+template <int SPL>
+__device__ __forceinline__ void store_pair(void* base, long long off, const Row<double, SPL>& row, int p) {
+    double2* q = reinterpret_cast<double2*>(base) + off;
+    q[0] = make_double2(row.re[2 * p], row.im[2 * p]);
+    q[1] = make_double2(row.re[2 * p + 1], row.im[2 * p + 1]);
+}
+template <int SPL>
+__device__ __forceinline__ void store_pair(void* base, long long off, const Row<float, SPL>& row, int p) {
+    *reinterpret_cast<float4*>(reinterpret_cast<float2*>(base) + off) =
+        make_float4(row.re[2 * p], row.im[2 * p], row.re[2 * p + 1], row.im[2 * p + 1]);
+}
+
+// ------------------------------------------------------------------ row operators
+
+// Which x-pairs of a lane exist.  Periodic meshes have every pair (the
+// struct is empty and the checks vanish); closed meshes have no pair that
+// crosses a wall: a lane whose pair reaches outside [0, nx) keeps those
+// sites unrotated (they hold zeros and are never stored).
+template <int PPL, bool CLOSED>
+struct XPairs {
+    bool even[PPL];      // (x, x+1) of pair p
+    bool inner[PPL];     // (x+1, x+2) inside the lane, p < PPL-1
+    bool left, right;    // odd pairs shared with the neighbouring lanes
+};
+template <int PPL>
+struct XPairs<PPL, false> {};
+
+template <class R>
+__device__ __forceinline__ void keep_old(bool ok, R& v, R old) {
+    v = ok ? v : old;
+}
+
+// Even x-pairs: inside the lane.
+template <bool CLOSED, class R, int SPL>
+__device__ __forceinline__ void even_x(Row<R, SPL>& w, R s, R d, const XPairs<SPL / 2, CLOSED>& m) {
+#pragma unroll
+    for (int p = 0; p < SPL / 2; ++p) {
+        const R a0 = w.re[2 * p], a1 = w.im[2 * p], b0 = w.re[2 * p + 1], b1 = w.im[2 * p + 1];
+        rot_pair(w.re[2 * p], w.im[2 * p], w.re[2 * p + 1], w.im[2 * p + 1], s, d);
+        if constexpr (CLOSED) {
+            keep_old(m.even[p], w.re[2 * p], a0);
+            keep_old(m.even[p], w.im[2 * p], a1);
+            keep_old(m.even[p], w.re[2 * p + 1], b0);
+            keep_old(m.even[p], w.im[2 * p + 1], b1);
+        } else {
+            (void)a0; (void)a1; (void)b0; (void)b1;
+        }
+    }
+}
+
+// Odd x-pairs: inner ones inside the lane, the two at the lane edges across lanes.
+template <bool CLOSED, class R, int SPL>
+__device__ __forceinline__ void odd_x(Row<R, SPL>& w, R s, R d, const XPairs<SPL / 2, CLOSED>& m) {
+    R rr = from_right(w.re[0]), ri = from_right(w.im[0]);
+    R lr = from_left(w.re[SPL - 1]), li = from_left(w.im[SPL - 1]);
+#pragma unroll
+    for (int p = 0; p + 1 < SPL / 2; ++p) {
+        const R a0 = w.re[2 * p + 1], a1 = w.im[2 * p + 1], b0 = w.re[2 * p + 2], b1 = w.im[2 * p + 2];
+        rot_pair(w.re[2 * p + 1], w.im[2 * p + 1], w.re[2 * p + 2], w.im[2 * p + 2], s, d);
+        if constexpr (CLOSED) {
+            keep_old(m.inner[p], w.re[2 * p + 1], a0);
+            keep_old(m.inner[p], w.im[2 * p + 1], a1);
+            keep_old(m.inner[p], w.re[2 * p + 2], b0);
+            keep_old(m.inner[p], w.im[2 * p + 2], b1);
+        } else {
+            (void)a0; (void)a1; (void)b0; (void)b1;
+        }
+    }
+    const R e0 = w.re[SPL - 1], e1 = w.im[SPL - 1], f0 = w.re[0], f1 = w.im[0];
+    rot_site(w.re[SPL - 1], w.im[SPL - 1], rr, ri, s, d);
+    rot_site(w.re[0], w.im[0], lr, li, s, d);
+    if constexpr (CLOSED) {
+        keep_old(m.right, w.re[SPL - 1], e0);
+        keep_old(m.right, w.im[SPL - 1], e1);
+        keep_old(m.left, w.re[0], f0);
+        keep_old(m.left, w.im[0], f1);
+    } else {
+        (void)e0; (void)e1; (void)f0; (void)f1;
+    }
+}
+
+// y-pair made of row `u` (upper, smaller y) and row `v` (next row).
+template <class R, int SPL>
+__device__ __forceinline__ void pair_y(Row<R, SPL>& u, Row<R, SPL>& v, R s, R d) {
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) rot_pair(u.re[i], u.im[i], v.re[i], v.im[i], s, d);
+}
+
+template <class PT, class R, int SPL>
+__device__ __forceinline__ void phase_row(Row<R, SPL>& w, const PT* p) {
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) apply_phase(w.re[i], w.im[i], p[i]);
+}
+
+template <class PT, int SPL>
+struct PhasePair {
+    PT top[SPL], bot[SPL];
+};
+
+__device__ __forceinline__ int wrap(long long v, int n) {
+    long long m = v % n;
+    return (int)(m < 0 ? m + n : m);
+}
+
+// One iteration of the S-stage pipeline.  On entry (it, ib) is the row pair
+// just loaded.  Marching down (REV = false), stage k completes pair t-1-k: the
+// odd factors on its boundary with the pair below it (whose top row arrives as
+// `it`), then, for k < S, the even factors and the phase on the pair itself
+// (phase rows from `phase(k)`).  Marching up (REV = true), stage k completes
+// pair t+1+k and the odd boundary is with the pair above (its bottom row
+// arrives as `ib`).  Each site sees the same operations in the same order in
+// both directions.  Stage K-1 = S of the last pass applies only the closing
+// odd factors.  On exit (it, ib) is the finished pair t-K (t+K marching up).
+// Closed meshes skip the y-pairs that cross a wall (`q` is the pair stage 0
+// completes; a wavefront-uniform test).
+template <int S, int K, bool REV, bool CLOSED, class R, int SPL, class PT, class PhaseFn>
+__device__ __forceinline__ void pipeline_step(Row<R, SPL> (&ht)[K], Row<R, SPL> (&hb)[K],
+                                              Row<R, SPL>& it, Row<R, SPL>& ib,
+                                              const MarchArgs<R>& a,
+                                              const XPairs<SPL / 2, CLOSED>& xm, int q,
+                                              PhaseFn&& phase) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        R oxs, oxd, oys, oyd;
+        if (k == 0) {
+            oxs = a.o1xs; oxd = a.o1xd; oys = a.o1ys; oyd = a.o1yd;
+        } else if (k < S) {
+            oxs = a.o2xs; oxd = a.o2xd; oys = a.o2ys; oyd = a.o2yd;
+        } else {
+            oxs = a.ehxs; oxd = a.ehxd; oys = a.ehys; oyd = a.ehyd;
+        }
+        const int qk = REV ? q + k : q - k;  // pair completed by stage k
+        // odd y-pair: rows (2qk+1, 2qk+2) marching down, (2qk-1, 2qk) marching up
+        const bool oy_ok = !CLOSED || (REV ? (qk >= 1 && 2 * qk < a.ny) : (qk >= 0 && 2 * qk + 2 < a.ny));
+        const bool ey_ok = !CLOSED || (qk >= 0 && 2 * qk + 1 < a.ny);
+        if constexpr (REV) {
+            odd_x<CLOSED>(ht[k], oxs, oxd, xm);
+            odd_x<CLOSED>(ib, oxs, oxd, xm);
+            if (oy_ok) pair_y(ib, ht[k], oys, oyd);
+        } else {
+            odd_x<CLOSED>(hb[k], oxs, oxd, xm);
+            odd_x<CLOSED>(it, oxs, oxd, xm);
+            if (oy_ok) pair_y(hb[k], it, oys, oyd);
+        }
+        if (k < S) {
+            const PhasePair<PT, SPL> ph = phase(k);
+            even_x<CLOSED>(ht[k], a.ehxs, a.ehxd, xm);
+            even_x<CLOSED>(hb[k], a.ehxs, a.ehxd, xm);
+            if (ey_ok) pair_y(ht[k], hb[k], a.ehys, a.ehyd);
+            phase_row(ht[k], ph.top);
+            phase_row(hb[k], ph.bot);
+            if (ey_ok) pair_y(ht[k], hb[k], a.ehys, a.ehyd);
+            even_x<CLOSED>(ht[k], a.ehxs, a.ehxd, xm);
+            even_x<CLOSED>(hb[k], a.ehxs, a.ehxd, xm);
+        }
+        Row<R, SPL> ot = ht[k], ob = hb[k];
+        ht[k] = it;
+        hb[k] = ib;
+        it = ot;
+        ib = ob;
+    }
+}
+
+// Phase factors of the S row pairs inside the pipeline, plus the pair entering
+// it, are held either in a register ring (LDS = false; the march loop is
+// unrolled by the ring length so slot indices are static) or in a per-lane
+// LDS ring (LDS = true; dynamic slots, no unrolling, for deep pipelines).
+// LDS ring of one wavefront: [slot][row][site][lane] phase factors.
+template <class T, int S, int PPL, bool LDS>
+struct WaveRing {
+    static constexpr int kSlots = LDS ? S + 1 : 1;  // 1 = unused
+    typename T::PT v[kSlots][2][2 * PPL][kWaveSize];
+};
+
+// Site-wise loads and stores for closed meshes (odd sides allowed, so rows
+// need not start on a 16-byte boundary; sites outside the mesh read as 0).
+__device__ __forceinline__ void load_site(const void* base, long long off, double& re, double& im) {
+    const double2 v = reinterpret_cast<const double2*>(base)[off];
+    re = v.x;
+    im = v.y;
+}
+__device__ __forceinline__ void load_site(const void* base, long long off, float& re, float& im) {
+    const float2 v = reinterpret_cast<const float2*>(base)[off];
+    re = v.x;
+    im = v.y;
+}
+__device__ __forceinline__ void store_site(void* base, long long off, double re, double im) {
+    reinterpret_cast<double2*>(base)[off] = make_double2(re, im);
+}
+__device__ __forceinline__ void store_site(void* base, long long off, float re, float im) {
+    reinterpret_cast<float2*>(base)[off] = make_float2(re, im);
+}
+template <class PT>
+__device__ __forceinline__ PT zero_phase() {
+    PT z;
+    if constexpr (sizeof(PT) == 16 && alignof(PT) == 16 && sizeof(z.x) == 4) {
+        z.x = z.y = z.z = z.w = 0.f;
+    } else {
+        z.x = z.y = 0.0;
+    }
+    return z;
+}
+
+// March one tile (strip, segment) of one pass; `ring` is this lane's column of
+// the wavefront's LDS ring (unused with the register ring).  REV marches the
+// segment upwards: odd segments do, so two neighbouring segments cross the
+// rows they both read (each other's warm-up halo) at the same time, start or
+// end, and the second read can hit L2.  CLOSED: hard walls instead of
+// periodic wrap (rows and columns outside the mesh are zeros that no
+// rotation touches).
+template <class T, int S, bool LAST, int PPL, bool LDS, bool REV, bool CLOSED>
+__device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, int strip, int seg,
+                                           int lane, typename T::PT* ring) {
+    using R = typename T::R;
+    using PT = typename T::PT;
+    constexpr int SPL = 2 * PPL;
+    constexpr int K = S + (LAST ? 1 : 0);
+    constexpr int HL = (K + PPL - 1) / PPL;
+    constexpr int NL = WaveRing<T, S, PPL, LDS>::kSlots;
+    const int nx = a.nx, ny = a.ny;
+
+    // x: unwrapped column of the lane's first site; wrapped (periodic) or
+    // unwrapped (closed) column of each pair; which sites exist and which
+    // lanes store.
+    const long long xu0 = (long long)strip * a.strip_sites + (long long)(lane - HL) * SPL;
+    const bool inner = lane >= HL && lane < kWaveSize - HL;
+    int col[PPL];
+    bool keep[PPL];
+    bool site_ok[SPL];
+    XPairs<PPL, CLOSED> xm;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        col[p] = CLOSED ? (int)(xu0 + 2 * p) : wrap(xu0 + 2 * p, nx);
+        keep[p] = inner && (xu0 + 2 * p) < nx;
+    }
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) site_ok[i] = !CLOSED || (xu0 + i >= 0 && xu0 + i < nx);
+    if constexpr (CLOSED) {
+        auto in = [&](long long x) { return x >= 0 && x < nx; };
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            xm.even[p] = in(xu0 + 2 * p) && in(xu0 + 2 * p + 1);
+            xm.inner[p] = in(xu0 + 2 * p + 1) && in(xu0 + 2 * p + 2);
+        }
+        xm.left = in(xu0 - 1) && in(xu0);
+        xm.right = in(xu0 + SPL - 1) && in(xu0 + SPL);
+    }
+
+    // y: output row pairs [q0, q1); input pairs [q0 - K, q1 - 1 + K], visited in
+    // increasing order (or decreasing when REV); `rnext` is the first row of the
+    // next pair to load, stepped by two rows (periodic wrap; closed meshes
+    // leave it unwrapped and treat rows outside [0, ny) as zeros).
+    const int hp = CLOSED ? (ny + 1) >> 1 : ny >> 1;
+    const int q0 = seg * (a.seg_rows >> 1);
+    const int q1 = min(q0 + (a.seg_rows >> 1), hp);
+    const int nit = (q1 - q0) + 2 * K;
+    const int tstart = REV ? q1 - 1 + K : q0 - K;
+    int rnext = CLOSED ? 2 * tstart : wrap(2LL * tstart, ny);
+    int qout = REV ? q1 - 1 + 2 * K : q0 - 2 * K;  // pair leaving the pipeline this iteration
+
+    Row<R, SPL> ht[K], hb[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) {
+            ht[k].re[i] = ht[k].im[i] = R(0);
+            hb[k].re[i] = hb[k].im[i] = R(0);
+        }
+    }
+
+    auto advance_row = [&]() {
+        if constexpr (REV) {
+            rnext -= 2;
+            if (!CLOSED && rnext < 0) rnext += ny;
+        } else {
+            rnext += 2;
+            if (!CLOSED && rnext >= ny) rnext -= ny;
+        }
+    };
+    auto load_row = [&](int r, Row<R, SPL>& w) {
+        if constexpr (CLOSED) {
+            const bool row_ok = r >= 0 && r < ny;
+            const long long off = (long long)r * nx + xu0;
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                w.re[i] = w.im[i] = R(0);
+                if (row_ok && site_ok[i]) load_site(a.src, off + i, w.re[i], w.im[i]);
+            }
+        } else {
+            const long long off = (long long)r * nx;
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) load_pair(a.src, off + col[p], w, p);
+        }
+    };
+    auto load_psi = [&](Row<R, SPL>& top, Row<R, SPL>& bot) {
+        load_row(rnext, top);
+        load_row(rnext + 1, bot);
+    };
+    auto load_phase_row = [&](int r, PT (&v)[SPL]) {
+        const PT* P = reinterpret_cast<const PT*>(a.ptab);
+        if constexpr (CLOSED) {
+            const bool row_ok = r >= 0 && r < ny;
+            const long long off = (long long)r * nx + xu0;
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) v[i] = (row_ok && site_ok[i]) ? P[off + i] : zero_phase<PT>();
+        } else {
+            const long long off = (long long)r * nx;
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                v[2 * p] = P[off + col[p]];
+                v[2 * p + 1] = P[off + col[p] + 1];
+            }
+        }
+    };
+    auto load_phase = [&]() {
+        PhasePair<PT, SPL> ph;
+        load_phase_row(rnext, ph.top);
+        load_phase_row(rnext + 1, ph.bot);
+        return ph;
+    };
+    auto store_out = [&](const Row<R, SPL>& top, const Row<R, SPL>& bot) {
+        const int qo = qout;
+        qout += REV ? -1 : 1;
+        if (REV ? (qo >= q1) : (qo < q0)) return;  // still warming up
+        const long long r0 = 2LL * qo;
+        if constexpr (CLOSED) {
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                if (inner && site_ok[i]) {
+                    store_site(a.dst, r0 * nx + xu0 + i, top.re[i], top.im[i]);
+                    if (r0 + 1 < ny) store_site(a.dst, (r0 + 1) * nx + xu0 + i, bot.re[i], bot.im[i]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                if (keep[p]) {
+                    store_pair(a.dst, r0 * nx + col[p], top, p);
+                    store_pair(a.dst, (r0 + 1) * nx + col[p], bot, p);
+                }
+            }
+        }
+    };
+
+    Row<R, SPL> nt, nbm;  // psi of the next pair (prefetched one iteration ahead)
+    int q = REV ? tstart + 1 : tstart - 1;  // pair stage 0 completes this iteration
+
+    if constexpr (!LDS) {
+        constexpr int NP = S + 2;
+        PhasePair<PT, SPL> pr[NP];
+        load_psi(nt, nbm);
+        pr[0] = load_phase();
+        advance_row();
+        for (int jb = 0; jb < nit; jb += NP) {
+#pragma unroll
+            for (int u = 0; u < NP; ++u) {
+                const int j = jb + u;
+                if (j >= nit) break;  // uniform per wavefront
+                Row<R, SPL> it = nt, ib = nbm;
+                if (j + 1 < nit) {
+                    load_psi(nt, nbm);
+                    pr[(u + 1) % NP] = load_phase();
+                    advance_row();
+                }
+                pipeline_step<S, K, REV, CLOSED, R, SPL, PT>(
+                    ht, hb, it, ib, a, xm, q, [&](int k) { return pr[(u - 1 - k + 2 * NP) % NP]; });
+                store_out(it, ib);
+                q += REV ? -1 : 1;
+            }
+        }
+    } else {
+        load_psi(nt, nbm);
+        PhasePair<PT, SPL> pn = load_phase();  // next pair's phase, in flight
+        advance_row();
+        constexpr int SLOT = 2 * SPL * kWaveSize;  // PT elements per slot
+        int wslot = 0;                             // slot of the pair entering the pipeline
+        for (int j = 0; j < nit; ++j) {
+            Row<R, SPL> it = nt, ib = nbm;
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                ring[wslot * SLOT + i * kWaveSize] = pn.top[i];
+                ring[wslot * SLOT + (SPL + i) * kWaveSize] = pn.bot[i];
+            }
+            if (j + 1 < nit) {
+                load_psi(nt, nbm);
+                pn = load_phase();
+                advance_row();
+            }
+            pipeline_step<S, K, REV, CLOSED, R, SPL, PT>(ht, hb, it, ib, a, xm, q, [&](int k) {
+                int slot = wslot - 1 - k;
+                if (slot < 0) slot += NL;
+                PhasePair<PT, SPL> ph;
+#pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    ph.top[i] = ring[slot * SLOT + i * kWaveSize];
+                    ph.bot[i] = ring[slot * SLOT + (SPL + i) * kWaveSize];
+                }
+                return ph;
+            });
+            store_out(it, ib);
+            q += REV ? -1 : 1;
+            wslot = (wslot + 1 == NL) ? 0 : wslot + 1;
+        }
+    }
+}
+
+// Odd segments march upwards (see march_tile).
+template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED>
+__device__ __forceinline__ void march_any(const MarchArgs<typename T::R>& a, int strip, int seg,
+                                          int lane, typename T::PT* ring) {
+    if (seg & 1)
+        march_tile<T, S, LAST, PPL, LDS, true, CLOSED>(a, strip, seg, lane, ring);
+    else
+        march_tile<T, S, LAST, PPL, LDS, false, CLOSED>(a, strip, seg, lane, ring);
+}
+
+// One problem, one tile per wavefront.
+template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED>
+__global__ void __launch_bounds__(kWaveSize * kWavesPerBlock)
+march_kernel(const MarchArgs<typename T::R> a) {
+    __shared__ WaveRing<T, S, PPL, LDS> rings[LDS ? kWavesPerBlock : 1];
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    // XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
+    // block b runs on XCD b % 8; give each XCD a contiguous run of tiles so
+    // the halo rows shared by neighbouring segments meet in one L2.
+    const int nb = gridDim.x;
+    const int full = nb & ~7;
+    const int b = blockIdx.x;
+    const int lb = (b < full) ? ((b & 7) * (full >> 3) + (b >> 3)) : b;
+    const long long tile = (long long)lb * kWavesPerBlock + wave;
+    if (tile >= (long long)a.nstrips * a.nsegs) return;  // uniform per wavefront
+    const int strip = (int)(tile / a.nsegs);
+    const int seg = (int)(tile - (long long)strip * a.nsegs);
+    march_any<T, S, LAST, PPL, LDS, CLOSED>(a, strip, seg, lane,
+                                            &rings[LDS ? wave : 0].v[0][0][0][lane]);
+}
+
+// Many problems: a fixed grid of wavefronts walks a work list of tiles
+// (job, strip, segment), wavefront w taking tiles w, w + W, w + 2W, ...; the
+// host sorts the list by tile height so the strided walk balances the load.
+template <class T, int S, bool LAST, int PPL, bool LDS>
+__global__ void __launch_bounds__(kWaveSize * kWavesPerBlock)
+march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
+                   const BatchTile* __restrict__ tiles, int ntiles) {
+    __shared__ WaveRing<T, S, PPL, LDS> rings[LDS ? kWavesPerBlock : 1];
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    const int nw = gridDim.x * kWavesPerBlock;
+    for (int i = blockIdx.x * kWavesPerBlock + wave; i < ntiles; i += nw) {
+        const BatchTile t = tiles[i];
+        const MarchArgs<typename T::R> a = jobs[t.job];
+        march_any<T, S, LAST, PPL, LDS, false>(a, t.strip, t.seg, lane,
+                                               &rings[LDS ? wave : 0].v[0][0][0][lane]);
+    }
+}
+
+// Instances: periodic register ring for 1..4 steps per pass (1 or 2 pairs
+// per lane), periodic LDS ring for 1..kMaxSteps (1 pair per lane), single
+// and batched; closed meshes: both rings with 1 pair per lane, single only.
+enum class Variant { Single, Batch, Closed };
+
+template <class T, int S, bool LAST, int PPL, bool LDS>
+const void* kernel_ptr(Variant v) {
+    switch (v) {
+        case Variant::Single:
+            return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, false>);
+        case Variant::Batch:
+            return reinterpret_cast<const void*>(&march_batch_kernel<T, S, LAST, PPL, LDS>);
+        case Variant::Closed:
+            if constexpr (PPL == 1)
+                return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, true>);
+            else
+                return nullptr;
+    }
+    return nullptr;
+}
+
+template <class T, bool LAST, int PPL, bool LDS, int... Ss>
+const void* pick_steps(int steps, Variant v, std::integer_sequence<int, Ss...>) {
+    const void* f = nullptr;
+    ((steps == Ss + 1 ? (f = kernel_ptr<T, Ss + 1, LAST, PPL, LDS>(v), 0) : 0), ...);
+    return f;
+}
+
+template <class T, bool LAST>
+const void* pick_variant(int steps, int ppl, bool lds, Variant v) {
+    if (lds) {
+        if (ppl != 1) return nullptr;
+        return pick_steps<T, LAST, 1, true>(steps, v, std::make_integer_sequence<int, kMaxSteps>());
+    }
+    if (ppl == 2)
+        return pick_steps<T, LAST, 2, false>(steps, v,
+                                             std::make_integer_sequence<int, kMaxRegSteps>());
+    return pick_steps<T, LAST, 1, false>(steps, v, std::make_integer_sequence<int, kMaxRegSteps>());
+}
+
+template <class T>
+const void* pick_kernel(int steps, bool last, int ppl, bool lds, Variant v) {
+    return last ? pick_variant<T, true>(steps, ppl, lds, v) : pick_variant<T, false>(steps, ppl, lds, v);
+}
+
+
+
+
+}  // namespace
+}  // namespace tsq

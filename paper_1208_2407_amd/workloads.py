@@ -246,3 +246,40 @@ def random_state(nx: int, ny: int, seed: int) -> np.ndarray:
 def random_potential(nx: int, ny: int, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return scale * rng.standard_normal((ny, nx))
+
+
+@dataclasses.dataclass
+class Request:
+    """One solve request of a served trace: arrival time (s) and its problem."""
+    rid: int
+    arrival: float
+    problem: Problem
+
+
+def request_trace(rate: float = 200.0, duration: float = 60.0, seed: int = 5, lo: int = 128,
+                  hi: int = 4096, steps_lo: int = 100, steps_hi: int = 2000,
+                  p_c64: float = 0.8) -> List[Request]:
+    """Poisson arrivals at `rate` per second for `duration` seconds.  Sides
+    log-uniform in [lo, hi] rounded to even (square with probability 1/2),
+    steps uniform in [steps_lo, steps_hi], complex64 with probability p_c64
+    else complex128, 1-4 seeded packets in a harmonic well plus bumps, dt from
+    {0.02, 0.05, 0.1}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out: List[Request] = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        square = rng.uniform() < 0.5
+        a = _even(math.exp(rng.uniform(math.log(lo), math.log(hi))), lo)
+        b = a if square else _even(math.exp(rng.uniform(math.log(lo), math.log(hi))), lo)
+        steps = int(rng.integers(steps_lo, steps_hi + 1))
+        dtype = "c64" if rng.uniform() < p_c64 else "c128"
+        dt = float(rng.choice([0.02, 0.05, 0.1]))
+        npk = int(rng.integers(1, 5))
+        sub = int(rng.integers(0, 2**31 - 1))
+        prob = packets_and_bumps(a, b, sub, dt, steps, dtype, n_packets=npk,
+                                 name=f"req{len(out)}_{a}x{b}")
+        out.append(Request(len(out), t, prob))
+    return out

@@ -33,11 +33,11 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version():
-    assert tsq.tsq_abi_version() == 1
+    assert tsq.tsq_abi_version() == 2
 
 
 def problem(**kw):
-    base = dict(nx=64, ny=32, dx=1.0, dy=1.0, mass=1.0, hbar=1.0, dt=0.1, bc=0, dtype=1)
+    base = dict(nx=64, ny=32, dx=1.0, dy=1.0, mass=1.0, hbar=1.0, dt=0.1, bc=0, dtype=1, order=2)
     base.update(kw)
     return tsq.tsq_problem(*[base[k] for k, _ in tsq.tsq_problem._fields_])
 
@@ -47,7 +47,8 @@ def problem(**kw):
     (dict(nx=65536, ny=65536), -2),
     (dict(dx=0.0), -1), (dict(dy=-1.0), -1), (dict(mass=math.nan), -1), (dict(hbar=math.inf), -1),
     (dict(dt=math.nan), -1), (dict(dt=math.inf), -1),
-    (dict(dtype=7), -3), (dict(bc=5), -1), (dict(bc=1), -7),
+    (dict(dtype=7), -3), (dict(bc=5), -1), (dict(order=3), -1),
+    (dict(order=1), -1),
 ])
 def test_plan_create_rejects(kw, status):
     with pytest.raises(tsq.TsqError) as ei:
@@ -114,6 +115,25 @@ def test_calls_reject_null_and_out_of_order_before_any_launch():
 
 
 @pytest.mark.parametrize("S,steps,passes,copy", [
+    (4, 1, 4, False),      # runs 2p | 1m | 2p at S=4: passes 1 + 1 + 1 = 3 -> one split -> 4
+    (1, 1, 5, True),       # five single sub-step passes, none can be split
+    (4, 3, 8, False),      # 2p m 4p m 4p m 2p: 1+1+1+1+1+1+1 = 7 -> split -> 8
+    (2, 2, 6, False),      # 2p m 4p m 2p at S=2: 1+1+2+1+1 = 6 passes
+])
+def test_pass_count_order4(S, steps, passes, copy):
+    h = tsq.tsq_plan_create(problem(order=4))
+    try:
+        tsq.tsq_plan_set_schedule(h, sched(S, 0, 0, 0))
+        assert tsq.tsq_evolve_passes(h, steps) == (passes, copy)
+        n4 = tsq.tsq_workspace_size(h)
+        h2 = tsq.tsq_plan_create(problem(order=2))
+        assert n4 >= tsq.tsq_workspace_size(h2) + 64 * 32 * 16   # a second phase table
+        tsq.tsq_plan_destroy(h2)
+    finally:
+        tsq.tsq_plan_destroy(h)
+
+
+@pytest.mark.parametrize("S,steps,passes,copy", [
     (4, 1000, 250, False), (4, 100, 26, False), (1, 7, 7, True), (4, 1, 1, True),
     (4, 3, 2, False), (3, 0, 0, False), (2, 5, 4, False), (1, 8, 8, False),
     (4, 10**12 + 4, 250000000002, False), (8, 1000, 126, False), (7, 14, 2, False),
@@ -123,5 +143,16 @@ def test_pass_count(S, steps, passes, copy):
     try:
         tsq.tsq_plan_set_schedule(h, sched(S, 0, 0, 0))
         assert tsq.tsq_evolve_passes(h, steps) == (passes, copy)
+    finally:
+        tsq.tsq_plan_destroy(h)
+
+
+def test_closed_meshes_accept_odd_sides_and_one_pair_per_lane():
+    h = tsq.tsq_plan_create(problem(nx=63, ny=33, bc=1))
+    try:
+        tsq.tsq_plan_set_schedule(h, sched(3, 0, 1, 0))
+        with pytest.raises(tsq.TsqError) as ei:
+            tsq.tsq_plan_set_schedule(h, sched(3, 0, 2, 1))
+        assert ei.value.status == -1
     finally:
         tsq.tsq_plan_destroy(h)

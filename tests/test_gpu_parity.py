@@ -189,3 +189,63 @@ def test_mesh4096_full_1000_steps():
     log(f"  mesh4096 1000 steps c64: rel L2 {e64:.3e}")
     assert e128 <= TOL["c128"]
     assert e64 <= TOL["c64"]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("S", [1, 2, 4, 6])
+def test_fourth_order_matches_oracle(dtype, S):
+    """U4(dt) = U2(p dt)^2 U2((1-4p) dt) U2(p dt)^2 (Eq. "fourthorder") on the GPU
+    against the oracle's literal five sub-steps per step."""
+    nx, ny = 130, 66
+    psi0 = wl.random_state(nx, ny, 41)
+    V = wl.random_potential(nx, ny, 42, scale=0.5)
+    for steps in (1, 4):
+        want = oracle_evolve(psi0, V, 0.11, steps, dtype, order=4, **ANISO)
+        got = gpu_evolve(psi0, V, 0.11, steps, dtype, steps_per_pass=S, order=4, **ANISO)
+        assert rel_l2(got, want) <= TOL[dtype], (S, steps)
+
+
+CLOSED_SHAPES = [(2, 2), (3, 5), (7, 4), (131, 67), (66, 301)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("S", [1, 3, 4, 7])
+@pytest.mark.parametrize("shape", CLOSED_SHAPES)
+def test_closed_meshes(shape, S, dtype):
+    """Hard walls (no wrap pair, odd sides allowed) against the oracle's closed mesh."""
+    nx, ny = shape
+    psi0 = wl.random_state(nx, ny, 50 + nx)
+    V = wl.random_potential(nx, ny, 51 + ny, scale=0.5)
+    stores = (1, 2) if S <= 4 else (2,)
+    for steps in (1, 6):
+        want = oracle_evolve(psi0, V, 0.11, steps, dtype, bc="closed", **ANISO)
+        for store in stores:
+            got = gpu_evolve(psi0, V, 0.11, steps, dtype, steps_per_pass=S, segment_rows=16,
+                             phase_store=store, bc="closed", **ANISO)
+            assert rel_l2(got, want) <= TOL[dtype], (shape, S, store, steps)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_closed_schedule_does_not_change_a_bit(dtype):
+    nx, ny = 131, 67
+    psi0 = wl.random_state(nx, ny, 60)
+    V = wl.random_potential(nx, ny, 61)
+    ref = gpu_evolve(psi0, V, 0.09, 9, dtype, steps_per_pass=1, segment_rows=2, phase_store=1,
+                     bc="closed")
+    for S in (2, 4, 5, 8):
+        for seg in (2, 10, 0):
+            got = gpu_evolve(psi0, V, 0.09, 9, dtype, steps_per_pass=S, segment_rows=seg,
+                             bc="closed")
+            assert np.array_equal(got, ref), (S, seg)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_closed_observables_match_oracle(dtype):
+    nx, ny = 131, 67
+    psi0 = as_input(wl.random_state(nx, ny, 62), dtype)
+    V = wl.random_potential(nx, ny, 63)
+    psi = torch.from_numpy(psi0).to(torch.complex128 if dtype == "c128" else torch.complex64).cuda()
+    plan = tsq.Plan(nx, ny, 0.1, dtype, bc="closed", device=psi.device, **ANISO)
+    n, e = plan.observables(psi, torch.from_numpy(V).cuda())
+    n0, e0 = oracle.observables(psi0, V, bc="closed", **ANISO)
+    assert abs(n - n0) <= 1e-13 * n0 and abs(e - e0) <= 1e-12 * max(1.0, abs(e0))
