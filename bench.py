@@ -283,7 +283,9 @@ def run_served(args) -> dict:
                    "block_steps": args.block_steps, "hbm_budget_bytes": srv.budget,
                    "schedules": {k: list(v) for k, v in serve.SCHEDULES.items()}},
         "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"],
-        "utilization": offered / st["site_steps_per_s"] if st["site_steps_per_s"] else None,
+        # 1.0 = the server kept up with the offered load (served everything as fast as
+        # it arrived); below 1 the queue grew over the trace
+        "served_over_offered": st["site_steps_per_s"] / offered if offered else None,
         "served": st,
         "fifo_comparison": {"trace_seconds": args.fifo_seconds, "batched": batched_prefix,
                             "fifo": fifo},

@@ -105,6 +105,7 @@ class Server:
         latencies: List[float] = []
         site_steps = 0
         admitted = rejected = iterations = max_resident = 0
+        side = torch.cuda.Stream(device=self.device)
         torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()
 
@@ -145,20 +146,26 @@ class Server:
                 admitted += 1
             max_resident = max(max_resident, len(resident))
             if resident and len(in_flight) < self.max_in_flight:
+                # complex64 requests on the current stream, complex128 ones on a side
+                # stream (default priority) so the two batched calls overlap
                 batches = []
-                for dtype in ("c64", "c128"):
+                cur = torch.cuda.current_stream(self.device)
+                side.wait_stream(cur)
+                for dtype, stream in (("c64", cur), ("c128", side)):
                     group = [s for s in resident if s.req.problem.dtype == dtype]
                     if not group:
                         continue
                     steps = [min(self.block, s.remaining) for s in group]
-                    b = tsq.Batch([s.plan for s in group], [s.psi for s in group], steps,
-                                  SCHEDULES[dtype])
-                    b.launch()
+                    with torch.cuda.stream(stream):
+                        b = tsq.Batch([s.plan for s in group], [s.psi for s in group], steps,
+                                      SCHEDULES[dtype])
+                        b.launch()
                     batches.append(b)
                     for s, n in zip(group, steps):
                         s.remaining -= n
+                cur.wait_stream(side)
                 ev = torch.cuda.Event()
-                ev.record()
+                ev.record(cur)
                 finishing = [s for s in resident if s.remaining == 0]
                 resident = [s for s in resident if s.remaining > 0]
                 in_flight.append((ev, batches, finishing))
