@@ -196,7 +196,7 @@ def run_batch(args) -> dict:
 
     # batch schedule: a short search over steps per pass (LDS ring, one pair per lane)
     best = None
-    for S in ([int(args.schedule.split(",")[0])] if args.schedule else (2, 3, 4, 6)):
+    for S in ([int(args.schedule.split(",")[0])] if args.schedule else (3, 4, 5, 6)):
         sched = (S, 0, 1, 2)
         psis = [x.clone() for x in psi0s]
         bt = tsq.Batch(plans, psis, steps, sched)

@@ -4,7 +4,7 @@
 namespace tsq {
 
 const void* march_ptr_c128_batch(int steps, bool last, int ppl, bool lds) {
-    return pick_kernel<C128>(steps, last, ppl, lds, Variant::Batch);
+    return pick_kernel<C128, Variant::Batch>(steps, last, ppl, lds);
 }
 
 }  // namespace tsq

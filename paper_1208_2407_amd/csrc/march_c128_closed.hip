@@ -4,7 +4,7 @@
 namespace tsq {
 
 const void* march_ptr_c128_closed(int steps, bool last, int ppl, bool lds) {
-    return pick_kernel<C128>(steps, last, ppl, lds, Variant::Closed);
+    return pick_kernel<C128, Variant::Closed>(steps, last, ppl, lds);
 }
 
 }  // namespace tsq

@@ -4,7 +4,7 @@
 namespace tsq {
 
 const void* march_ptr_c128_single(int steps, bool last, int ppl, bool lds) {
-    return pick_kernel<C128>(steps, last, ppl, lds, Variant::Single);
+    return pick_kernel<C128, Variant::Single>(steps, last, ppl, lds);
 }
 
 }  // namespace tsq

@@ -4,7 +4,7 @@
 namespace tsq {
 
 const void* march_ptr_c64_batch(int steps, bool last, int ppl, bool lds) {
-    return pick_kernel<C64>(steps, last, ppl, lds, Variant::Batch);
+    return pick_kernel<C64, Variant::Batch>(steps, last, ppl, lds);
 }
 
 }  // namespace tsq

@@ -4,7 +4,7 @@
 namespace tsq {
 
 const void* march_ptr_c64_closed(int steps, bool last, int ppl, bool lds) {
-    return pick_kernel<C64>(steps, last, ppl, lds, Variant::Closed);
+    return pick_kernel<C64, Variant::Closed>(steps, last, ppl, lds);
 }
 
 }  // namespace tsq

@@ -4,7 +4,7 @@
 namespace tsq {
 
 const void* march_ptr_c64_single(int steps, bool last, int ppl, bool lds) {
-    return pick_kernel<C64>(steps, last, ppl, lds, Variant::Single);
+    return pick_kernel<C64, Variant::Single>(steps, last, ppl, lds);
 }
 
 }  // namespace tsq

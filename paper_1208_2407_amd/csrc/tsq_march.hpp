@@ -295,7 +295,8 @@ __device__ __forceinline__ void pipeline_step(Row<R, SPL> (&ht)[K], Row<R, SPL> 
 // LDS ring of one wavefront: [slot][row][site][lane] phase factors.
 template <class T, int S, int PPL, bool LDS>
 struct WaveRing {
-    static constexpr int kSlots = LDS ? S + 1 : 1;  // 1 = unused
+    // stage 0 takes its phase from registers; stages 1..S-1 from S-1 slots
+    static constexpr int kSlots = (LDS && S > 1) ? S - 1 : 1;
     typename T::PT v[kSlots][2][2 * PPL][kWaveSize];
 };
 
@@ -497,24 +498,27 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         }
     } else {
         load_psi(nt, nbm);
-        PhasePair<PT, SPL> pn = load_phase();  // next pair's phase, in flight
+        PhasePair<PT, SPL> pn = load_phase();  // phase of the next pair, in flight
         advance_row();
+        // Stage 0 reads the phase of its pair from registers (p0); at the end of
+        // iteration j that phase moves to LDS slot j mod (S-1), where stage k
+        // reads it in iteration j + k.
+        PhasePair<PT, SPL> p0;
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) p0.top[i] = p0.bot[i] = zero_phase<PT>();
         constexpr int SLOT = 2 * SPL * kWaveSize;  // PT elements per slot
-        int wslot = 0;                             // slot of the pair entering the pipeline
+        int wslot = 0;                             // slot written at the end of this iteration
         for (int j = 0; j < nit; ++j) {
             Row<R, SPL> it = nt, ib = nbm;
-#pragma unroll
-            for (int i = 0; i < SPL; ++i) {
-                ring[wslot * SLOT + i * kWaveSize] = pn.top[i];
-                ring[wslot * SLOT + (SPL + i) * kWaveSize] = pn.bot[i];
-            }
+            const PhasePair<PT, SPL> arrived = pn;  // phase of pair `it`, used from next iteration
             if (j + 1 < nit) {
                 load_psi(nt, nbm);
                 pn = load_phase();
                 advance_row();
             }
             pipeline_step<S, K, REV, CLOSED, R, SPL, PT>(ht, hb, it, ib, a, xm, q, [&](int k) {
-                int slot = wslot - 1 - k;
+                if (k == 0) return p0;
+                int slot = wslot - k;
                 if (slot < 0) slot += NL;
                 PhasePair<PT, SPL> ph;
 #pragma unroll
@@ -526,7 +530,15 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
             });
             store_out(it, ib);
             q += REV ? -1 : 1;
-            wslot = (wslot + 1 == NL) ? 0 : wslot + 1;
+            if constexpr (S > 1) {
+#pragma unroll
+                for (int i = 0; i < SPL; ++i) {
+                    ring[wslot * SLOT + i * kWaveSize] = p0.top[i];
+                    ring[wslot * SLOT + (SPL + i) * kWaveSize] = p0.bot[i];
+                }
+                wslot = (wslot + 1 == NL) ? 0 : wslot + 1;
+            }
+            p0 = arrived;
         }
     }
 }
@@ -587,48 +599,43 @@ march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
 // and batched; closed meshes: both rings with 1 pair per lane, single only.
 enum class Variant { Single, Batch, Closed };
 
-template <class T, int S, bool LAST, int PPL, bool LDS>
-const void* kernel_ptr(Variant v) {
-    switch (v) {
-        case Variant::Single:
-            return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, false>);
-        case Variant::Batch:
-            return reinterpret_cast<const void*>(&march_batch_kernel<T, S, LAST, PPL, LDS>);
-        case Variant::Closed:
-            if constexpr (PPL == 1)
-                return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, true>);
-            else
-                return nullptr;
-    }
-    return nullptr;
+template <class T, int S, bool LAST, int PPL, bool LDS, Variant V>
+const void* kernel_ptr() {
+    if constexpr (V == Variant::Single)
+        return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, false>);
+    else if constexpr (V == Variant::Batch)
+        return reinterpret_cast<const void*>(&march_batch_kernel<T, S, LAST, PPL, LDS>);
+    else if constexpr (PPL == 1)
+        return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, true>);
+    else
+        return nullptr;
 }
 
-template <class T, bool LAST, int PPL, bool LDS, int... Ss>
-const void* pick_steps(int steps, Variant v, std::integer_sequence<int, Ss...>) {
+template <class T, Variant V, bool LAST, int PPL, bool LDS, int... Ss>
+const void* pick_steps(int steps, std::integer_sequence<int, Ss...>) {
     const void* f = nullptr;
-    ((steps == Ss + 1 ? (f = kernel_ptr<T, Ss + 1, LAST, PPL, LDS>(v), 0) : 0), ...);
+    ((steps == Ss + 1 ? (f = kernel_ptr<T, Ss + 1, LAST, PPL, LDS, V>(), 0) : 0), ...);
     return f;
 }
 
-template <class T, bool LAST>
-const void* pick_variant(int steps, int ppl, bool lds, Variant v) {
+template <class T, Variant V, bool LAST>
+const void* pick_variant(int steps, int ppl, bool lds) {
     if (lds) {
         if (ppl != 1) return nullptr;
-        return pick_steps<T, LAST, 1, true>(steps, v, std::make_integer_sequence<int, kMaxSteps>());
+        return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxSteps>());
     }
-    if (ppl == 2)
-        return pick_steps<T, LAST, 2, false>(steps, v,
-                                             std::make_integer_sequence<int, kMaxRegSteps>());
-    return pick_steps<T, LAST, 1, false>(steps, v, std::make_integer_sequence<int, kMaxRegSteps>());
+    if (ppl == 2) {
+        if constexpr (V == Variant::Closed) return nullptr;
+        return pick_steps<T, V, LAST, 2, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
+    }
+    return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
 }
 
-template <class T>
-const void* pick_kernel(int steps, bool last, int ppl, bool lds, Variant v) {
-    return last ? pick_variant<T, true>(steps, ppl, lds, v) : pick_variant<T, false>(steps, ppl, lds, v);
+// Kernel of one instance of variant V (instantiates only that variant).
+template <class T, Variant V>
+const void* pick_kernel(int steps, bool last, int ppl, bool lds) {
+    return last ? pick_variant<T, V, true>(steps, ppl, lds) : pick_variant<T, V, false>(steps, ppl, lds);
 }
-
-
-
 
 }  // namespace
 }  // namespace tsq

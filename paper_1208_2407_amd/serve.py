@@ -33,7 +33,7 @@ import torch
 import paper_1208_2407_amd as tsq
 from paper_1208_2407_amd import workloads as wl
 
-SCHEDULES = {"c64": (4, 0, 1, 2), "c128": (6, 0, 1, 2)}
+SCHEDULES = {"c64": (6, 0, 1, 2), "c128": (6, 0, 1, 2)}
 
 
 def request_bytes(p: wl.Problem) -> int:
