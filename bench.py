@@ -105,6 +105,9 @@ def run_dtype(dtype: str, p, psi0, V, args):
     launch_s = evolve_ms * 1e-3 / (args.steps * passes)
     achieved = alg_bytes / launch_s / 1e9
     traffic = committed_traffic(dtype, sched)
+    # one pass per step would need the same bytes every step: site-steps/s times those
+    # bytes over the peak says how far fusion takes the solve past that roofline (> 1)
+    eff_frac = (site_steps / wall) * (2 * elem + 16) / (HBM_PEAK_GBS * 1e9)
     log(f"{dtype}: {wall / args.steps * 1e3:.2f} ms/solve, {site_steps / wall:.4e} site-steps/s, "
         f"pass {launch_s * 1e6:.1f} us, {achieved:.0f} GB/s algorithmic, norm {norm:.15f}")
     del ws
@@ -118,6 +121,8 @@ def run_dtype(dtype: str, p, psi0, V, args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     "traffic_GBps": round(traffic / launch_s / 1e9, 1) if traffic else None,
+                     "eff_frac_one_pass_per_step": round(eff_frac, 3),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel": "march_kernel", "avg_launch_us": round(launch_s * 1e6, 2)},
         "norm_drift": norm - n_begin,
