@@ -62,6 +62,11 @@ class tsq_problem(ctypes.Structure):
 _lib = None
 
 
+def library_path() -> str:
+    """Path of the kernel library this module loads."""
+    return LIB_PATH
+
+
 def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     """Load libtsq.so (built in-tree by ``python -m paper_1208_2407_amd.build``)."""
     global _lib

@@ -15,12 +15,14 @@ from typing import Dict, Iterable, List, Optional, Tuple
 
 Schedule = Tuple[int, int, int, int]
 
-# segment_rows 0 = one round of resident wavefronts; phase_store 1 = registers, 2 = LDS
+# segment_rows 0 = one round of resident wavefronts; phase_store 1 = registers, 2 = LDS.
+# Not tried by default: 2 pairs per lane (twice the registers, one wavefront
+# per SIMD) and 7 or 8 steps per pass (a march loop larger than the
+# instruction cache); both stay available through tsq_plan_set_schedule.
 DEFAULT_CANDIDATES: List[Schedule] = (
-    [(S, 0, 1, store) for S in (1, 2, 3, 4) for store in (1, 2)]
-    + [(S, 0, 1, 2) for S in (5, 6, 7, 8)]
-    + [(S, 0, 2, 1) for S in (1, 2)]
-    + [(S, 96, 1, 2) for S in (4, 6)]
+    [(1, 0, 1, 1)]
+    + [(S, 0, 1, store) for S in (2, 3, 4) for store in (1, 2)]
+    + [(S, 0, 1, 2) for S in (5, 6)]
 )
 
 
@@ -29,8 +31,19 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "tsq", "autotune.json"))
 
 
+def _library_stamp() -> str:
+    """Size and modification time of the loaded kernel library: a rebuilt
+    library invalidates the cached choices."""
+    from . import library_path
+    try:
+        st = os.stat(library_path())
+        return f"{st.st_size}:{int(st.st_mtime)}"
+    except OSError:
+        return "?"
+
+
 def _key(arch: str, dtype: str, nx: int, ny: int) -> str:
-    return f"{arch}|{dtype}|{nx}x{ny}"
+    return f"{arch}|{dtype}|{nx}x{ny}|{_library_stamp()}"
 
 
 def _load() -> Dict[str, dict]:

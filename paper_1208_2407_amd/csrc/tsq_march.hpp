@@ -27,6 +27,7 @@
 
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "tsq_internal.h"
@@ -40,12 +41,13 @@ __device__ __forceinline__ float mad(float a, float b, float c) { return __built
 __device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // DPP wavefront shifts: lane i receives lane i-1 (from_left) or i+1 (from_right).
-// Lanes without a source receive 0; they lie in the discarded halo.
+// Lanes without a source receive 0 (bound_ctrl); they lie in the discarded
+// halo.
 __device__ __forceinline__ int dpp_from_left(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int dpp_from_right(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
 }
 __device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_from_left(__float_as_int(v))); }
 __device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_from_right(__float_as_int(v))); }
@@ -57,11 +59,11 @@ __device__ __forceinline__ double from_right(double v) {
 }
 
 // One site of a 2x2 block exponential [[c, i s], [i s, c]] with its partner b:
-//   a <- a + (i s b - d a),   d = 1 - c.
+//   a <- (a - d a) + i s b,   d = 1 - c.
 template <class R>
 __device__ __forceinline__ void rot_site(R& ar, R& ai, R br, R bi, R s, R d) {
-    R nr = mad(-d, ar, mad(-s, bi, ar));
-    R ni = mad(-d, ai, mad(s, br, ai));
+    R nr = mad(-s, bi, mad(-d, ar, ar));
+    R ni = mad(s, br, mad(-d, ai, ai));
     ar = nr;
     ai = ni;
 }
@@ -125,16 +127,23 @@ __device__ __forceinline__ void load_pair(const void* base, long long off, Row<f
     row.re[2 * p] = a.x; row.im[2 * p] = a.y;
     row.re[2 * p + 1] = a.z; row.im[2 * p + 1] = a.w;
 }
+// Stores are nontemporal: a pass writes each site once and nothing reads it
+// back before the next pass, so the lines should not displace the halo rows
+// that neighbouring tiles re-read from L2.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float4 __attribute__((ext_vector_type(4)));
 template <int SPL>
 __device__ __forceinline__ void store_pair(void* base, long long off, const Row<double, SPL>& row, int p) {
-    double2* q = reinterpret_cast<double2*>(base) + off;
-    q[0] = make_double2(row.re[2 * p], row.im[2 * p]);
-    q[1] = make_double2(row.re[2 * p + 1], row.im[2 * p + 1]);
+    nt_double2* q = reinterpret_cast<nt_double2*>(base) + off;
+    const nt_double2 a = {row.re[2 * p], row.im[2 * p]};
+    const nt_double2 b = {row.re[2 * p + 1], row.im[2 * p + 1]};
+    __builtin_nontemporal_store(a, q);
+    __builtin_nontemporal_store(b, q + 1);
 }
 template <int SPL>
 __device__ __forceinline__ void store_pair(void* base, long long off, const Row<float, SPL>& row, int p) {
-    *reinterpret_cast<float4*>(reinterpret_cast<float2*>(base) + off) =
-        make_float4(row.re[2 * p], row.im[2 * p], row.re[2 * p + 1], row.im[2 * p + 1]);
+    const nt_float4 v = {row.re[2 * p], row.im[2 * p], row.re[2 * p + 1], row.im[2 * p + 1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_float4*>(reinterpret_cast<float2*>(base) + off));
 }
 
 // ------------------------------------------------------------------ row operators
@@ -219,9 +228,42 @@ __device__ __forceinline__ void phase_row(Row<R, SPL>& w, const PT* p) {
     for (int i = 0; i < SPL; ++i) apply_phase(w.re[i], w.im[i], p[i]);
 }
 
+// Calls f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>());
+}
+// f(integral_constant<int, i>) for i = 0 .. N-1 while the calls return true;
+// true if all did.
+template <class F, int... Is>
+__device__ __forceinline__ bool static_all_impl(F&& f, std::integer_sequence<int, Is...>) {
+    return (f(std::integral_constant<int, Is>{}) && ...);
+}
+template <int N, class F>
+__device__ __forceinline__ bool static_all(F&& f) {
+    return static_all_impl(f, std::make_integer_sequence<int, N>());
+}
+
+// Row pairs of a march are named by the direction of travel: row F of a pair
+// faces the pairs marched before it, row G the pairs marched after it.
+// Marching down (increasing y) F is the pair's top row 2t and G its bottom
+// row 2t+1; marching up the two swap.  The odd y-pair joining an older pair
+// to the next newer one is (G of the older, F of the newer) either way, and
+// the rotation of a pair is symmetric in its two sites, so one code path
+// serves both directions with every site seeing the same operations in the
+// same order.
+template <class R, int SPL>
+struct PairRows {
+    Row<R, SPL> f, g;
+};
+
 template <class PT, int SPL>
 struct PhasePair {
-    PT top[SPL], bot[SPL];
+    PT f[SPL], g[SPL];
 };
 
 __device__ __forceinline__ int wrap(long long v, int n) {
@@ -229,73 +271,52 @@ __device__ __forceinline__ int wrap(long long v, int n) {
     return (int)(m < 0 ? m + n : m);
 }
 
-// One iteration of the S-stage pipeline.  On entry (it, ib) is the row pair
-// just loaded.  Marching down (REV = false), stage k completes pair t-1-k: the
-// odd factors on its boundary with the pair below it (whose top row arrives as
-// `it`), then, for k < S, the even factors and the phase on the pair itself
-// (phase rows from `phase(k)`).  Marching up (REV = true), stage k completes
-// pair t+1+k and the odd boundary is with the pair above (its bottom row
-// arrives as `ib`).  Each site sees the same operations in the same order in
-// both directions.  Stage K-1 = S of the last pass applies only the closing
-// odd factors.  On exit (it, ib) is the finished pair t-K (t+K marching up).
-// Closed meshes skip the y-pairs that cross a wall (`q` is the pair stage 0
-// completes; a wavefront-uniform test).
-template <int S, int K, bool REV, bool CLOSED, class R, int SPL, class PT, class PhaseFn>
-__device__ __forceinline__ void pipeline_step(Row<R, SPL> (&ht)[K], Row<R, SPL> (&hb)[K],
-                                              Row<R, SPL>& it, Row<R, SPL>& ib,
-                                              const MarchArgs<R>& a,
-                                              const XPairs<SPL / 2, CLOSED>& xm, int q,
-                                              PhaseFn&& phase) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        R oxs, oxd, oys, oyd;
-        if (k == 0) {
-            oxs = a.o1xs; oxd = a.o1xd; oys = a.o1ys; oyd = a.o1yd;
-        } else if (k < S) {
-            oxs = a.o2xs; oxd = a.o2xd; oys = a.o2ys; oyd = a.o2yd;
-        } else {
-            oxs = a.ehxs; oxd = a.ehxd; oys = a.ehys; oyd = a.ehyd;
-        }
-        const int qk = REV ? q + k : q - k;  // pair completed by stage k
-        // odd y-pair: rows (2qk+1, 2qk+2) marching down, (2qk-1, 2qk) marching up
-        const bool oy_ok = !CLOSED || (REV ? (qk >= 1 && 2 * qk < a.ny) : (qk >= 0 && 2 * qk + 2 < a.ny));
-        const bool ey_ok = !CLOSED || (qk >= 0 && 2 * qk + 1 < a.ny);
-        if constexpr (REV) {
-            odd_x<CLOSED>(ht[k], oxs, oxd, xm);
-            odd_x<CLOSED>(ib, oxs, oxd, xm);
-            if (oy_ok) pair_y(ib, ht[k], oys, oyd);
-        } else {
-            odd_x<CLOSED>(hb[k], oxs, oxd, xm);
-            odd_x<CLOSED>(it, oxs, oxd, xm);
-            if (oy_ok) pair_y(hb[k], it, oys, oyd);
-        }
-        if (k < S) {
-            const PhasePair<PT, SPL> ph = phase(k);
-            even_x<CLOSED>(ht[k], a.ehxs, a.ehxd, xm);
-            even_x<CLOSED>(hb[k], a.ehxs, a.ehxd, xm);
-            if (ey_ok) pair_y(ht[k], hb[k], a.ehys, a.ehyd);
-            phase_row(ht[k], ph.top);
-            phase_row(hb[k], ph.bot);
-            if (ey_ok) pair_y(ht[k], hb[k], a.ehys, a.ehyd);
-            even_x<CLOSED>(ht[k], a.ehxs, a.ehxd, xm);
-            even_x<CLOSED>(hb[k], a.ehxs, a.ehxd, xm);
-        }
-        Row<R, SPL> ot = ht[k], ob = hb[k];
-        ht[k] = it;
-        hb[k] = ib;
-        it = ot;
-        ib = ob;
+// Stage k of the S-stage pipeline.  `o` is the older row pair, the one stage
+// k completes; `n` is the newer pair right behind it, just finished by stage
+// k-1 (or just loaded, for k = 0).  Stage k applies the odd factors on the
+// boundary of the two (o's G row and n's F row; n's G row gets the same
+// factors in stage k+1, where n is the older pair), then, for k < S, step
+// k+1's even factors and the potential phase on o.  Stage K-1 = S of the last pass applies only the
+// closing odd factors.  Closed meshes skip the y-pairs that cross a wall
+// (`qk` is the pair stage k completes; a wavefront-uniform test).
+template <int S, int K, bool CLOSED, class R, int SPL, class PT, class PhaseFn>
+__device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
+                                               const MarchArgs<R>& a,
+                                               const XPairs<SPL / 2, CLOSED>& xm, int qk, bool rev,
+                                               PhaseFn&& phase) {
+    R oxs, oxd, oys, oyd;
+    if (k == 0) {
+        oxs = a.o1xs; oxd = a.o1xd; oys = a.o1ys; oyd = a.o1yd;
+    } else if (k < S) {
+        oxs = a.o2xs; oxd = a.o2xd; oys = a.o2ys; oyd = a.o2yd;
+    } else {
+        oxs = a.ehxs; oxd = a.ehxd; oys = a.ehys; oyd = a.ehyd;
+    }
+    // odd y-pair: rows (2qk+1, 2qk+2) marching down, (2qk-1, 2qk) marching up
+    const bool oy_ok = !CLOSED || (rev ? (qk >= 1 && 2 * qk < a.ny) : (qk >= 0 && 2 * qk + 2 < a.ny));
+    const bool ey_ok = !CLOSED || (qk >= 0 && 2 * qk + 1 < a.ny);
+    odd_x<CLOSED>(o.g, oxs, oxd, xm);
+    odd_x<CLOSED>(n.f, oxs, oxd, xm);
+    if (oy_ok) pair_y(o.g, n.f, oys, oyd);
+    if (k < S) {
+        const PhasePair<PT, SPL> ph = phase(k);
+        even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
+        even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
+        if (ey_ok) pair_y(o.f, o.g, a.ehys, a.ehyd);
+        phase_row(o.f, ph.f);
+        phase_row(o.g, ph.g);
+        if (ey_ok) pair_y(o.f, o.g, a.ehys, a.ehyd);
+        even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
+        even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
     }
 }
 
-// Phase factors of the S row pairs inside the pipeline, plus the pair entering
-// it, are held either in a register ring (LDS = false; the march loop is
-// unrolled by the ring length so slot indices are static) or in a per-lane
-// LDS ring (LDS = true; dynamic slots, no unrolling, for deep pipelines).
+// Phase factors of the row pairs inside the pipeline are held either in
+// registers (LDS = false) or, for stages 1..S-1, in a per-lane LDS ring
+// (LDS = true; stage 0 reads registers).
 // LDS ring of one wavefront: [slot][row][site][lane] phase factors.
 template <class T, int S, int PPL, bool LDS>
 struct WaveRing {
-    // stage 0 takes its phase from registers; stages 1..S-1 from S-1 slots
     static constexpr int kSlots = (LDS && S > 1) ? S - 1 : 1;
     typename T::PT v[kSlots][2][2 * PPL][kWaveSize];
 };
@@ -330,21 +351,33 @@ __device__ __forceinline__ PT zero_phase() {
 }
 
 // March one tile (strip, segment) of one pass; `ring` is this lane's column of
-// the wavefront's LDS ring (unused with the register ring).  REV marches the
+// the wavefront's LDS ring (unused with register phases).  `rev` marches the
 // segment upwards: odd segments do, so two neighbouring segments cross the
 // rows they both read (each other's warm-up halo) at the same time, start or
 // end, and the second read can hit L2.  CLOSED: hard walls instead of
 // periodic wrap (rows and columns outside the mesh are zeros that no
 // rotation touches).
-template <class T, int S, bool LAST, int PPL, bool LDS, bool REV, bool CLOSED>
+//
+// Register homes: the row pair that enters the pipeline in iteration j lives
+// in home j mod NH until it is stored K iterations later; stage k of
+// iteration j works on homes j-1-k (older) and j-k (newer), and the pair for
+// iteration j+1 is loaded into home j+1 meanwhile, so NH = K+2 homes suffice
+// and the march loop, unrolled by NH, moves no data between registers.
+// Phases: the phase rows of pair j are loaded in iteration j and first used
+// by stage 0 in iteration j+1; register phases keep one home per psi home,
+// the LDS ring keeps two register homes (pairs j and j-1) and moves pair
+// j-1's phase to the ring at the end of iteration j.
+template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED>
 __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, int strip, int seg,
-                                           int lane, typename T::PT* ring) {
+                                           bool rev, int lane, typename T::PT* ring) {
     using R = typename T::R;
     using PT = typename T::PT;
     constexpr int SPL = 2 * PPL;
     constexpr int K = S + (LAST ? 1 : 0);
     constexpr int HL = (K + PPL - 1) / PPL;
     constexpr int NL = WaveRing<T, S, PPL, LDS>::kSlots;
+    constexpr int NH = LDS ? ((K + 3) & ~1) : K + 2;  // even with the LDS ring
+    constexpr int NP = LDS ? 2 : NH;                   // phase homes
     const int nx = a.nx, ny = a.ny;
 
     // x: unwrapped column of the lane's first site; wrapped (periodic) or
@@ -375,34 +408,26 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     }
 
     // y: output row pairs [q0, q1); input pairs [q0 - K, q1 - 1 + K], visited in
-    // increasing order (or decreasing when REV); `rnext` is the first row of the
-    // next pair to load, stepped by two rows (periodic wrap; closed meshes
-    // leave it unwrapped and treat rows outside [0, ny) as zeros).
+    // increasing order (decreasing when marching up).  `rpsi` and `rph` are the
+    // first rows of the next pair whose psi, respectively phase, is loaded,
+    // stepped by two rows (periodic wrap; closed meshes leave them unwrapped
+    // and treat rows outside [0, ny) as zeros).
     const int hp = CLOSED ? (ny + 1) >> 1 : ny >> 1;
     const int q0 = seg * (a.seg_rows >> 1);
     const int q1 = min(q0 + (a.seg_rows >> 1), hp);
     const int nit = (q1 - q0) + 2 * K;
-    const int tstart = REV ? q1 - 1 + K : q0 - K;
-    int rnext = CLOSED ? 2 * tstart : wrap(2LL * tstart, ny);
-    int qout = REV ? q1 - 1 + 2 * K : q0 - 2 * K;  // pair leaving the pipeline this iteration
+    const int tstart = rev ? q1 - 1 + K : q0 - K;
+    const int fo = rev ? 1 : 0;  // row offset of F within a pair; G is at 1 - fo
+    int rpsi = CLOSED ? 2 * tstart : wrap(2LL * tstart, ny);
+    int rph = rpsi;
+    int qout = rev ? q1 - 1 + 2 * K : q0 - 2 * K;  // pair leaving the pipeline this iteration
 
-    Row<R, SPL> ht[K], hb[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) {
-            ht[k].re[i] = ht[k].im[i] = R(0);
-            hb[k].re[i] = hb[k].im[i] = R(0);
-        }
-    }
-
-    auto advance_row = [&]() {
-        if constexpr (REV) {
-            rnext -= 2;
-            if (!CLOSED && rnext < 0) rnext += ny;
-        } else {
-            rnext += 2;
-            if (!CLOSED && rnext >= ny) rnext -= ny;
+    const int rstep = rev ? -2 : 2;
+    auto step_row = [&](int& r) {
+        r += rstep;
+        if constexpr (!CLOSED) {
+            r = r < 0 ? r + ny : r;
+            r = r >= ny ? r - ny : r;
         }
     };
     auto load_row = [&](int r, Row<R, SPL>& w) {
@@ -420,9 +445,10 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
             for (int p = 0; p < PPL; ++p) load_pair(a.src, off + col[p], w, p);
         }
     };
-    auto load_psi = [&](Row<R, SPL>& top, Row<R, SPL>& bot) {
-        load_row(rnext, top);
-        load_row(rnext + 1, bot);
+    auto load_psi = [&](PairRows<R, SPL>& h) {
+        load_row(rpsi + fo, h.f);
+        load_row(rpsi + 1 - fo, h.g);
+        step_row(rpsi);
     };
     auto load_phase_row = [&](int r, PT (&v)[SPL]) {
         const PT* P = reinterpret_cast<const PT*>(a.ptab);
@@ -440,117 +466,102 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
             }
         }
     };
-    auto load_phase = [&]() {
-        PhasePair<PT, SPL> ph;
-        load_phase_row(rnext, ph.top);
-        load_phase_row(rnext + 1, ph.bot);
-        return ph;
+    auto load_phase = [&](PhasePair<PT, SPL>& ph) {
+        load_phase_row(rph + fo, ph.f);
+        load_phase_row(rph + 1 - fo, ph.g);
+        step_row(rph);
     };
-    auto store_out = [&](const Row<R, SPL>& top, const Row<R, SPL>& bot) {
+    auto store_out = [&](const PairRows<R, SPL>& h) {
         const int qo = qout;
-        qout += REV ? -1 : 1;
-        if (REV ? (qo >= q1) : (qo < q0)) return;  // still warming up
-        const long long r0 = 2LL * qo;
+        qout += rev ? -1 : 1;
+        if (rev ? (qo >= q1) : (qo < q0)) return;  // still warming up
+        const long long rf = 2LL * qo + fo, rg = 2LL * qo + 1 - fo;
         if constexpr (CLOSED) {
 #pragma unroll
             for (int i = 0; i < SPL; ++i) {
                 if (inner && site_ok[i]) {
-                    store_site(a.dst, r0 * nx + xu0 + i, top.re[i], top.im[i]);
-                    if (r0 + 1 < ny) store_site(a.dst, (r0 + 1) * nx + xu0 + i, bot.re[i], bot.im[i]);
+                    if (rf < ny) store_site(a.dst, rf * nx + xu0 + i, h.f.re[i], h.f.im[i]);
+                    if (rg < ny) store_site(a.dst, rg * nx + xu0 + i, h.g.re[i], h.g.im[i]);
                 }
             }
         } else {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
                 if (keep[p]) {
-                    store_pair(a.dst, r0 * nx + col[p], top, p);
-                    store_pair(a.dst, (r0 + 1) * nx + col[p], bot, p);
+                    store_pair(a.dst, rf * nx + col[p], h.f, p);
+                    store_pair(a.dst, rg * nx + col[p], h.g, p);
                 }
             }
         }
     };
 
-    Row<R, SPL> nt, nbm;  // psi of the next pair (prefetched one iteration ahead)
-    int q = REV ? tstart + 1 : tstart - 1;  // pair stage 0 completes this iteration
-
-    if constexpr (!LDS) {
-        constexpr int NP = S + 2;
-        PhasePair<PT, SPL> pr[NP];
-        load_psi(nt, nbm);
-        pr[0] = load_phase();
-        advance_row();
-        for (int jb = 0; jb < nit; jb += NP) {
+    PairRows<R, SPL> home[NH];
+    PhasePair<PT, SPL> ph[NP];
 #pragma unroll
-            for (int u = 0; u < NP; ++u) {
-                const int j = jb + u;
-                if (j >= nit) break;  // uniform per wavefront
-                Row<R, SPL> it = nt, ib = nbm;
-                if (j + 1 < nit) {
-                    load_psi(nt, nbm);
-                    pr[(u + 1) % NP] = load_phase();
-                    advance_row();
-                }
-                pipeline_step<S, K, REV, CLOSED, R, SPL, PT>(
-                    ht, hb, it, ib, a, xm, q, [&](int k) { return pr[(u - 1 - k + 2 * NP) % NP]; });
-                store_out(it, ib);
-                q += REV ? -1 : 1;
-            }
-        }
-    } else {
-        load_psi(nt, nbm);
-        PhasePair<PT, SPL> pn = load_phase();  // phase of the next pair, in flight
-        advance_row();
-        // Stage 0 reads the phase of its pair from registers (p0); at the end of
-        // iteration j that phase moves to LDS slot j mod (S-1), where stage k
-        // reads it in iteration j + k.
-        PhasePair<PT, SPL> p0;
+    for (int h = 0; h < NH; ++h) {
 #pragma unroll
-        for (int i = 0; i < SPL; ++i) p0.top[i] = p0.bot[i] = zero_phase<PT>();
-        constexpr int SLOT = 2 * SPL * kWaveSize;  // PT elements per slot
-        int wslot = 0;                             // slot written at the end of this iteration
-        for (int j = 0; j < nit; ++j) {
-            Row<R, SPL> it = nt, ib = nbm;
-            const PhasePair<PT, SPL> arrived = pn;  // phase of pair `it`, used from next iteration
-            if (j + 1 < nit) {
-                load_psi(nt, nbm);
-                pn = load_phase();
-                advance_row();
-            }
-            pipeline_step<S, K, REV, CLOSED, R, SPL, PT>(ht, hb, it, ib, a, xm, q, [&](int k) {
-                if (k == 0) return p0;
-                int slot = wslot - k;
-                if (slot < 0) slot += NL;
-                PhasePair<PT, SPL> ph;
-#pragma unroll
-                for (int i = 0; i < SPL; ++i) {
-                    ph.top[i] = ring[slot * SLOT + i * kWaveSize];
-                    ph.bot[i] = ring[slot * SLOT + (SPL + i) * kWaveSize];
-                }
-                return ph;
-            });
-            store_out(it, ib);
-            q += REV ? -1 : 1;
-            if constexpr (S > 1) {
-#pragma unroll
-                for (int i = 0; i < SPL; ++i) {
-                    ring[wslot * SLOT + i * kWaveSize] = p0.top[i];
-                    ring[wslot * SLOT + (SPL + i) * kWaveSize] = p0.bot[i];
-                }
-                wslot = (wslot + 1 == NL) ? 0 : wslot + 1;
-            }
-            p0 = arrived;
+        for (int i = 0; i < SPL; ++i) {
+            home[h].f.re[i] = home[h].f.im[i] = R(0);
+            home[h].g.re[i] = home[h].g.im[i] = R(0);
         }
     }
-}
+#pragma unroll
+    for (int h = 0; h < NP; ++h) {
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) ph[h].f[i] = ph[h].g[i] = zero_phase<PT>();
+    }
 
-// Odd segments march upwards (see march_tile).
-template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED>
-__device__ __forceinline__ void march_any(const MarchArgs<typename T::R>& a, int strip, int seg,
-                                          int lane, typename T::PT* ring) {
-    if (seg & 1)
-        march_tile<T, S, LAST, PPL, LDS, true, CLOSED>(a, strip, seg, lane, ring);
-    else
-        march_tile<T, S, LAST, PPL, LDS, false, CLOSED>(a, strip, seg, lane, ring);
+    constexpr int SLOT = 2 * SPL * kWaveSize;  // PT elements per LDS slot
+    int wslot = 0;  // LDS slot receiving the phase of pair j-1 at the end of iteration j
+    int q = rev ? tstart + 1 : tstart - 1;  // pair stage 0 completes this iteration
+    const int qend = rev ? q - nit : q + nit;  // ... one past the last iteration
+    load_psi(home[0]);
+    // One march iteration with static home indices (u = j mod NH).
+    auto iteration = [&](auto U) {
+        constexpr int u = decltype(U)::value;
+        // The last iteration loads one pair more than the march uses (a row
+        // of the mesh, or zeros outside a closed mesh): an unconditional load
+        // keeps the homes free of merges.
+        load_psi(home[(u + 1) % NH]);
+        load_phase(ph[u % NP]);
+        static_for<K>([&](auto KK) {
+            constexpr int k = decltype(KK)::value;
+            pipeline_stage<S, K, CLOSED, R, SPL, PT>(
+                k, home[(u - 1 - k + 2 * NH) % NH], home[(u - k + 2 * NH) % NH], a, xm,
+                rev ? q + k : q - k, rev, [&](int kk) {
+                    if (!LDS || kk == 0) return ph[(u - 1 - kk + 2 * NP) % NP];
+                    int slot = wslot - kk;
+                    if (slot < 0) slot += NL;
+                    PhasePair<PT, SPL> r;
+#pragma unroll
+                    for (int i = 0; i < SPL; ++i) {
+                        r.f[i] = ring[slot * SLOT + i * kWaveSize];
+                        r.g[i] = ring[slot * SLOT + (SPL + i) * kWaveSize];
+                    }
+                    return r;
+                });
+            // keep each stage's phase reads and temporaries inside the stage:
+            // hoisting them across stages costs more registers than it hides
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        store_out(home[(u - K + 2 * NH) % NH]);
+        q += rev ? -1 : 1;
+        if constexpr (LDS && S > 1) {
+            const PhasePair<PT, SPL>& p0 = ph[(u - 1 + 2 * NP) % NP];
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) {
+                ring[wslot * SLOT + i * kWaveSize] = p0.f[i];
+                ring[wslot * SLOT + (SPL + i) * kWaveSize] = p0.g[i];
+            }
+            wslot = (wslot + 1 == NL) ? 0 : wslot + 1;
+        }
+        return q != qend;  // another iteration follows
+    };
+    // nit >= 2K >= 2 iterations; each round runs NH of them and the march
+    // leaves right after the last (a wavefront-uniform exit, with no path
+    // that carries the homes past it).
+    while (static_all<NH>(iteration)) {
+    }
 }
 
 // One problem, one tile per wavefront.
@@ -571,8 +582,8 @@ march_kernel(const MarchArgs<typename T::R> a) {
     if (tile >= (long long)a.nstrips * a.nsegs) return;  // uniform per wavefront
     const int strip = (int)(tile / a.nsegs);
     const int seg = (int)(tile - (long long)strip * a.nsegs);
-    march_any<T, S, LAST, PPL, LDS, CLOSED>(a, strip, seg, lane,
-                                            &rings[LDS ? wave : 0].v[0][0][0][lane]);
+    march_tile<T, S, LAST, PPL, LDS, CLOSED>(a, strip, seg, seg & 1, lane,
+                                             &rings[LDS ? wave : 0].v[0][0][0][lane]);
 }
 
 // Many problems: a fixed grid of wavefronts walks a work list of tiles
@@ -589,8 +600,8 @@ march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
     for (int i = blockIdx.x * kWavesPerBlock + wave; i < ntiles; i += nw) {
         const BatchTile t = tiles[i];
         const MarchArgs<typename T::R> a = jobs[t.job];
-        march_any<T, S, LAST, PPL, LDS, false>(a, t.strip, t.seg, lane,
-                                               &rings[LDS ? wave : 0].v[0][0][0][lane]);
+        march_tile<T, S, LAST, PPL, LDS, false>(a, t.strip, t.seg, t.seg & 1, lane,
+                                                &rings[LDS ? wave : 0].v[0][0][0][lane]);
     }
 }
 
