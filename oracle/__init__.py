@@ -49,6 +49,8 @@ def load_library(path: str):
     d, i, ll, p = ctypes.c_double, ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p
     lib.tso_evolve.argtypes = [i, i, i, d, d, d, d, d, p, p, ll, i]
     lib.tso_evolve.restype = i
+    lib.tso_evolve_td.argtypes = [i, i, i, d, d, d, d, d, p, p, p, p, ll]
+    lib.tso_evolve_td.restype = i
     lib.tso_apply_factor.argtypes = [i, i, i, d, d, d, d, i, i, d, p, p]
     lib.tso_apply_factor.restype = i
     lib.tso_observables.argtypes = [i, i, i, d, d, d, d, p, p,
@@ -100,6 +102,23 @@ def evolve(psi0, V, dt, steps, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
     ny, nx = psi.shape
     rc = _load().tso_evolve(nx, ny, BC[bc], dx, dy, mass, hbar, dt,
                             v.ctypes.data, psi.ctypes.data, int(steps), int(order))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return psi
+
+
+def evolve_td(psi0, V0, W, f, dt, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
+              bc="periodic") -> np.ndarray:
+    """Return psi after len(f) steps of U2(dt) under V(t) = V0 + f(t) W, step n
+    using f[n] = f(t_n + dt/2) (the potential at the step's midpoint)."""
+    psi = _as_psi(psi0)
+    v0 = _as_v(V0, psi.shape)
+    w = _as_v(W, psi.shape)
+    fv = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1))
+    ny, nx = psi.shape
+    rc = _load().tso_evolve_td(nx, ny, BC[bc], dx, dy, mass, hbar, dt, v0.ctypes.data,
+                               w.ctypes.data, fv.ctypes.data if fv.size else None,
+                               psi.ctypes.data, int(fv.size))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return psi

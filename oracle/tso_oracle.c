@@ -202,6 +202,37 @@ int tso_evolve(int nx, int ny, int bc, double dx, double dy, double mass, double
     return 0;
 }
 
+/*
+ * Time-dependent potential V(t) = V0 + f(t) W.  The paper builds the product
+ * for a time-independent H and notes that the time-dependent form is the same
+ * construction (Sec. 2, footnote to Eq. "evolution", citing Poulin et al.):
+ * step n, from t_n to t_n + dt, is U2(dt) with H frozen at the step's
+ * midpoint, which keeps the product second order for smooth f.  The caller
+ * gives f[n] = f(t_n + dt/2) for n = 0 .. steps-1; the potential of step n is
+ * V0 + f[n] W.  Order 2 only.  Returns 0, or -1 on a bad argument (psi
+ * untouched).
+ */
+int tso_evolve_td(int nx, int ny, int bc, double dx, double dy, double mass, double hbar,
+                  double dt, const double *V0, const double *W, const double *f, double *psi,
+                  long long steps) {
+    if (!sides_ok(nx, ny, bc) || !params_ok(dx, dy, mass, hbar) || !isfinite(dt) ||
+        steps < 0 || V0 == NULL || W == NULL || psi == NULL || (steps > 0 && f == NULL))
+        return -1;
+    for (long long n = 0; n < steps; ++n)
+        if (!isfinite(f[n])) return -1;
+    size_t sites = (size_t)nx * (size_t)ny;
+    double *Vn = (double *)malloc(sites * sizeof(double));
+    if (!Vn) return -1;
+    for (long long n = 0; n < steps; ++n) {
+        long long l;
+#pragma omp parallel for schedule(static)
+        for (l = 0; l < (long long)sites; ++l) Vn[l] = V0[l] + f[n] * W[l];
+        u2_step(nx, ny, bc, dx, dy, mass, hbar, dt, Vn, psi);
+    }
+    free(Vn);
+    return 0;
+}
+
 /* Apply one single factor, for tests of the operator structure:
  *   which = 0: Kx(parity, tau)   1: Ky(parity, tau)   2: P(tau) */
 int tso_apply_factor(int nx, int ny, int bc, double dx, double dy, double mass, double hbar,

@@ -28,6 +28,9 @@ MUTANTS = {
     "y factors use the x spacing": [("block_coeffs(h, Jy, hbar, &sy, &dyc);", "block_coeffs(h, Jx, hbar, &sy, &dyc);")],
     "energy hop sign": [("hr -= Jx * psi[2 * m];", "hr += Jx * psi[2 * m];")],
     "norm drops the imaginary part": [("sn += pr * pr + pi * pi;", "sn += pr * pr;")],
+    "time-dependent modulation ignored": [("Vn[l] = V0[l] + f[n] * W[l];", "Vn[l] = V0[l] + 0.0 * W[l];")],
+    "modulation lags one step": [("Vn[l] = V0[l] + f[n] * W[l];", "Vn[l] = V0[l] + f[n > 0 ? n - 1 : 0] * W[l];")],
+    "modulation without the time step": [("Vn[l] = V0[l] + f[n] * W[l];", "Vn[l] = V0[l] + f[n] * W[l] / dt;")],
     "energy misses y neighbours": [("hr -= Jy * psi[2 * m];", "hr -= 0.0 * psi[2 * m];"),
                                    ("hi -= Jy * psi[2 * m + 1];", "hi -= 0.0 * psi[2 * m + 1];")],
 }
@@ -42,6 +45,8 @@ CHECKS = [
     lambda: pins.test_bloch_closed_form((16, 16), 7),
     lambda: pins.test_plane_wave_energy((3, 1)),
     lambda: pins.test_energy_equals_dense_expectation((6, 4), "periodic"),
+    lambda: pins.test_td_error_shrinks_as_dt_squared((6, 4), "periodic"),
+    lambda: pins.test_td_step_equals_dense_product_of_frozen_steps(),
 ]
 
 

@@ -276,3 +276,109 @@ def test_thread_count_does_not_change_results():
     oracle.set_threads(nthreads)
     np.testing.assert_array_equal(a, b)
     assert na == nb
+
+
+# ---------------------------------------------------------------- time-dependent potential
+# V(t) = V0 + f(t) W, step n frozen at its midpoint (the time-dependent form the
+# paper defers to, Sec. 2 footnote).  The reference here is the Schroedinger
+# equation itself, integrated by an adaptive Runge-Kutta method: no splitting,
+# no exponential.
+
+def _td_drive(t):
+    return 0.7 * np.sin(1.3 * t + 0.4)
+
+
+def _td_exact(nx, ny, V0, W, psi, t_end, bc, **kw):
+    from scipy.integrate import solve_ivp
+    hbar = kw.get("hbar", 1.0)
+    H0 = dense.full_h(nx, ny, V0, bc=bc, **kw)
+    w = np.asarray(W, dtype=float).reshape(-1)
+
+    def rhs(t, y):
+        return (-1j / hbar) * (H0 @ y + _td_drive(t) * (w * y))
+
+    sol = solve_ivp(rhs, (0.0, t_end), psi.reshape(-1).astype(complex), method="DOP853",
+                    rtol=1e-13, atol=1e-15)
+    assert sol.success
+    return sol.y[:, -1].reshape(ny, nx)
+
+
+@pytest.mark.parametrize("shape,bc", [((6, 4), "periodic"), ((5, 4), "closed")])
+def test_td_error_shrinks_as_dt_squared(shape, bc):
+    """With f sampled at step midpoints the product stays second order against
+    the time-ordered solution of i hbar dpsi/dt = H(t) psi."""
+    nx, ny = shape
+    V0 = wl.random_potential(nx, ny, 61)
+    W = wl.random_potential(nx, ny, 62)
+    psi = wl.random_state(nx, ny, 63)
+    t = 1.0
+    exact = _td_exact(nx, ny, V0, W, psi, t, bc, **ANISO)
+    errs = []
+    for N in (8, 16, 32, 64):
+        dt = t / N
+        f = _td_drive((np.arange(N) + 0.5) * dt)
+        errs.append(rel(oracle.evolve_td(psi, V0, W, f, dt, bc=bc, **ANISO), exact))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    for r in ratios:
+        assert abs(r - 4.0) < 0.15, (errs, ratios)
+
+
+def test_td_zero_modulation_is_the_static_evolution():
+    nx, ny = 12, 10
+    V0 = wl.random_potential(nx, ny, 64)
+    W = wl.random_potential(nx, ny, 65)
+    psi = wl.random_state(nx, ny, 66)
+    got = oracle.evolve_td(psi, V0, W, np.zeros(9), 0.23, **ANISO)
+    np.testing.assert_array_equal(got, oracle.evolve(psi, V0, 0.23, 9, **ANISO))
+
+
+def test_td_uniform_modulation_is_a_global_phase():
+    """W = c everywhere commutes with everything: the result is the static one
+    times exp(-i dt c sum_n f_n / hbar)."""
+    nx, ny = 16, 12
+    V0 = wl.random_potential(nx, ny, 67)
+    psi = wl.random_state(nx, ny, 68)
+    c, dt = 0.83, 0.19
+    f = np.random.default_rng(69).uniform(-1.0, 1.0, 23)
+    got = oracle.evolve_td(psi, V0, np.full((ny, nx), c), f, dt, **ANISO)
+    want = oracle.evolve(psi, V0, dt, f.size, **ANISO) * np.exp(-1j * dt * c * f.sum() / ANISO["hbar"])
+    assert rel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("bc", ["periodic", "closed"])
+def test_td_forward_then_backward_is_identity(bc):
+    """Each step is U2(dt) of its own frozen H, and U2(-dt) inverts it; running
+    the steps back in reverse order with -dt returns the initial state."""
+    nx, ny = 14, 10
+    V0 = wl.random_potential(nx, ny, 70)
+    W = wl.random_potential(nx, ny, 71)
+    psi = wl.random_state(nx, ny, 72)
+    f = np.random.default_rng(73).uniform(-2.0, 2.0, 30)
+    fwd = oracle.evolve_td(psi, V0, W, f, 0.3, bc=bc, **ANISO)
+    back = oracle.evolve_td(fwd, V0, W, f[::-1], -0.3, bc=bc, **ANISO)
+    assert rel(back, psi) < 1e-13
+    assert abs(np.sum(np.abs(fwd) ** 2) - np.sum(np.abs(psi) ** 2)) < 1e-13
+
+
+def test_td_step_equals_dense_product_of_frozen_steps():
+    """Step n is the dense nine-factor product with V0 + f_n W on the diagonal."""
+    nx, ny = 6, 4
+    V0 = wl.random_potential(nx, ny, 74)
+    W = wl.random_potential(nx, ny, 75)
+    psi = wl.random_state(nx, ny, 76)
+    dt = 0.27
+    f = np.array([0.3, -1.1, 0.8])
+    want = psi.reshape(-1).astype(complex)
+    for fn in f:
+        want = dense.u2_dense(nx, ny, V0 + fn * W, dt, **ANISO) @ want
+    got = oracle.evolve_td(psi, V0, W, f, dt, **ANISO)
+    assert rel(got, want.reshape(ny, nx)) < 1e-13
+
+
+def test_td_rejects_bad_arguments():
+    psi = wl.random_state(6, 4, 1)
+    V = np.zeros((4, 6))
+    with pytest.raises(ValueError):
+        oracle.evolve_td(psi, V, V, [0.0, np.nan], 0.1)
+    with pytest.raises(ValueError):
+        oracle.evolve_td(psi, V, np.zeros((4, 5)), [0.0], 0.1)
