@@ -130,6 +130,82 @@ def run_dtype(dtype: str, p, psi0, V, args):
     }
 
 
+def run_td(dtype: str, p, psi0, V0, W, f, args):
+    """One solve under the time-dependent potential V0 + f(t) W: table setup,
+    len(f) fused steps (the phase formed in FP64 in the march), FP64 observables
+    at the final time."""
+    import torch
+    import paper_1208_2407_amd as tsq
+
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    psi = psi0.to(tdt).contiguous()
+    plan = tsq.Plan(p.nx, p.ny, p.dt, dtype, device=psi.device)
+    plan.set_potential_td(V0, W)
+    if args.schedule:
+        plan.set_schedule(*[int(v) for v in args.schedule.split(",")])
+    else:
+        scratch = psi.clone()
+        best = None
+        for cand in [(S, 0, 1, st) for S in (1, 2, 3, 4) for st in (1, 2)]:
+            plan.set_schedule(*cand)
+            plan.evolve_td(scratch, f[:8])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.evolve_td(scratch, f[:120])
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            if args.verbose:
+                log(f"td {dtype} S={cand[0]} store={cand[3]}: {ms:.3f} ms / 120 steps")
+            if best is None or ms < best[0]:
+                best = (ms, cand)
+        plan.set_schedule(*best[1])
+        del scratch
+    sched = plan.schedule()
+    passes, copy_back = plan.passes(len(f))
+    V_end = V0 + float(f[-1]) * W   # potential at the last step's midpoint, for the energy
+
+    def solve(events=None):
+        plan.set_potential_td(V0, W)
+        if events is not None:
+            events[0].record()
+        plan.evolve_td(psi, f)
+        if events is not None:
+            events[1].record()
+        return plan.observables(psi, V_end)
+
+    n_begin, _ = plan.observables(psi, V_end)
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        norm, energy = solve(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evolve_ms = sum(a.elapsed_time(b) for a, b in evs)
+    site_steps = p.nx * p.ny * len(f) * args.steps
+    elem = 16 if dtype == "c128" else 8
+    alg_bytes = p.nx * p.ny * (2 * elem + 16)   # read psi, write psi, read (theta0, w)
+    launch_s = evolve_ms * 1e-3 / (args.steps * passes)
+    achieved = alg_bytes / launch_s / 1e9
+    log(f"td {dtype}: S={sched[0]} store={sched[3]}: {wall / args.steps * 1e3:.2f} ms/solve, "
+        f"{site_steps / wall:.4e} site-steps/s, pass {launch_s * 1e6:.1f} us, norm {norm:.15f}")
+    return {
+        "value": site_steps / wall, "ms_per_step": wall / args.steps * 1e3,
+        "schedule": {"steps_per_pass": sched[0], "pairs_per_lane": sched[2],
+                     "phase_store": {1: "registers", 2: "lds"}[sched[3]],
+                     "passes_per_solve": passes, "copy_back": copy_back},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": alg_bytes, "kernel": "march_kernel (td)",
+                     "avg_launch_us": round(launch_s * 1e6, 2)},
+        "norm_drift": norm - n_begin,
+    }
+
+
 def profile_mode(p, psi0, V, args) -> int:
     """A short, fixed run for hardware-counter collection (no tuning, no timing loop)."""
     import torch
@@ -327,10 +403,11 @@ def main() -> int:
     ap.add_argument("--dtypes", default="c64,c128")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--workload", default="mesh4096",
-                    choices=["mesh4096", "mesh32768", "batch512", "served"],
+                    choices=["mesh4096", "mesh32768", "batch512", "served", "td4096"],
                     help="mesh4096: the benchmark line; mesh32768: 32768^2 complex64, 200 "
                          "steps; batch512: 512 uneven complex64 problems, 500 steps; "
-                         "served: Poisson request stream into the batching server")
+                         "served: Poisson request stream into the batching server; td4096: "
+                         "the 4096^2 workload under a time-dependent potential")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--fifo-seconds", type=float, default=10.0)
     ap.add_argument("--block-steps", type=int, default=24)
@@ -366,6 +443,30 @@ def main() -> int:
                            "mesh": [p.nx, p.ny], "time_steps_per_solve": p.steps, "dt": p.dt,
                            **r["schedule"]},
                 "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
+        print(json.dumps(line), flush=True)
+        return 0
+    if args.workload == "td4096":
+        p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 1000, "c64", name="packets_bumps_4096")
+        log("generating inputs on the device")
+        psi0 = wl.initial_state(p, device="cuda")
+        V0 = wl.potential(p, device="cuda")
+        W = wl.standing_wave(p, device="cuda")
+        f = wl.drive(p.dt, p.steps)
+        res = {d: run_td(d, p, psi0, V0, W, f, args) for d in args.dtypes.split(",")}
+        r = res["c64"] if "c64" in res else next(iter(res.values()))
+        line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "c64" if "c64" in res else "c128", "data": "synthetic",
+                "config": {"workload": "packets_bumps_4096x4096_dt0.05_1000steps_shaken_standing_wave",
+                           "mesh": [p.nx, p.ny], "time_steps_per_solve": p.steps, "dt": p.dt,
+                           "drive": "V0 + 0.2 sin(0.5 t) cos(8 pi i / 4096) at column i", **r["schedule"]},
+                "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
+        if "c128" in res and "c64" in res:
+            rr = res["c128"]
+            line["complex128"] = {"dtype": "c128", "value": rr["value"], "unit": "site-steps/s",
+                                  "ms_per_step": rr["ms_per_step"], "config": rr["schedule"],
+                                  "roofline": rr["roofline"], "norm_drift": rr["norm_drift"]}
         print(json.dumps(line), flush=True)
         return 0
     p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 1000, "c64", name="packets_bumps_4096")

@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define TSQ_ABI_VERSION 2
+#define TSQ_ABI_VERSION 3
 
 typedef enum {
     TSQ_OK = 0,
@@ -136,7 +136,8 @@ typedef struct {
 int tsq_plan_set_schedule(tsq_plan* plan, const tsq_schedule* schedule);
 int tsq_plan_get_schedule(const tsq_plan* plan, tsq_schedule* schedule);
 
-/* Number of kernel launches (fused passes) tsq_evolve makes for `steps`
+/* Number of kernel launches (fused passes) tsq_evolve (or, after
+ * tsq_set_potential_td, tsq_evolve_td) makes for `steps`
  * under the plan's schedule, and whether it ends with a device-to-device copy
  * (odd pass count that cannot be split).  Host only.  Errors: TSQ_ERR_ARG. */
 int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int32_t* copy_back);
@@ -152,9 +153,39 @@ int tsq_set_potential(tsq_plan* plan, const double* V_dev, void* ws, size_t ws_b
 /* Rows a1-a6: apply U2(dt)^steps (order 4: U4(dt)^steps) to psi_dev in place (device, contiguous,
  * 16-byte aligned).  steps == 0 returns TSQ_OK without a launch.
  * Errors: TSQ_ERR_ARG (null, steps < 0, misaligned psi), TSQ_ERR_STATE (no
- * potential set, or a different workspace), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
+ * potential set, a different workspace, or a time-dependent table from
+ * tsq_set_potential_td), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
 int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws_bytes,
                void* stream);
+
+/* ---------------------------------------------------------------- time-dependent potential
+ * V(t) = V0 + f(t) W.  The paper states the product for a time-independent
+ * Hamiltonian and notes that the time-dependent form is the same construction
+ * (Sec. 2, footnote to Eq. "evolution", citing Poulin et al.): here step n,
+ * from t_n to t_n + dt, is U2(dt) with the potential frozen at the step's
+ * midpoint, V0 + f_n W with f_n = f(t_n + dt/2), which keeps the product second
+ * order for smooth f.  Periodic order-2 plans only; every step's phase factor
+ * exp(-i dt (V0 + f_n W + eps0) / hbar) is formed in FP64 inside the march, so
+ * up to 4 steps fuse per pass (a plan scheduled deeper runs 4). */
+
+/* Store the time-dependent table of V0_dev and W_dev (device, nx*ny doubles
+ * each) in `ws`: per site dt (V0 + eps0) / hbar and dt W / hbar (16 bytes, the
+ * place of the phase table).  Records `ws` for tsq_evolve_td; a later
+ * tsq_set_potential makes the workspace time-independent again.
+ * Errors: TSQ_ERR_ARG (null), TSQ_ERR_UNSUPPORTED (order 4 or closed mesh),
+ * TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
+int tsq_set_potential_td(tsq_plan* plan, const double* V0_dev, const double* W_dev, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Apply `steps` steps to psi_dev in place; step n uses f_host[n] (host array of
+ * `steps` finite doubles, read before the call returns) as the modulation at
+ * its midpoint.  Consecutive calls continue the evolution: pass each call the
+ * modulations of its own steps.  Results are bitwise identical across
+ * schedules.  Errors: TSQ_ERR_ARG (null, steps < 0, a non-finite f, 2 pairs
+ * per lane, misaligned psi), TSQ_ERR_STATE (tsq_set_potential_td not called
+ * with this workspace), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
+int tsq_evolve_td(tsq_plan* plan, void* psi_dev, int64_t steps, const double* f_host, void* ws,
+                  size_t ws_bytes, void* stream);
 
 /* Row a7: FP64 norm N = sum |psi_l|^2 and energy E = <psi|H|psi> / N of the
  * lattice Hamiltonian H = diag(V + eps0) - Jx (x-neighbours) - Jy
@@ -180,7 +211,8 @@ typedef struct tsq_batch tsq_batch; /* opaque, host memory */
 /* Build a batch of n problems (host only): problem i is plans[i] applied to
  * psi_dev[i] with workspace ws[i] (tsq_set_potential must already have been
  * called with that workspace) for steps[i] >= 0 steps.  All plans must have
- * the same dtype and be periodic and of order 2 (else TSQ_ERR_UNSUPPORTED).
+ * the same dtype and be periodic and of order 2, with a time-independent
+ * potential (else TSQ_ERR_UNSUPPORTED).
  * `schedule` (NULL = defaults; segment_rows is ignored, the
  * batch sizes its own tiles) applies to every problem.  The batch records the
  * device pointers, which must stay valid while it is used; plans may be

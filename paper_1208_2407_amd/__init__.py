@@ -29,7 +29,8 @@ BCS = {"periodic": 0, "closed": 1}
 
 EXPORTED = ("tsq_abi_version", "tsq_last_error", "tsq_plan_create", "tsq_plan_destroy",
             "tsq_workspace_size", "tsq_plan_set_schedule", "tsq_plan_get_schedule",
-            "tsq_evolve_passes", "tsq_set_potential", "tsq_evolve", "tsq_observables",
+            "tsq_evolve_passes", "tsq_set_potential", "tsq_evolve", "tsq_set_potential_td",
+            "tsq_evolve_td", "tsq_observables",
             "tsq_batch_create", "tsq_batch_destroy", "tsq_batch_workspace_size", "tsq_batch_info",
             "tsq_batch_upload", "tsq_batch_launch")
 
@@ -89,6 +90,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.tsq_evolve_passes.argtypes = [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.tsq_set_potential.argtypes = [vp, vp, vp, sz, vp]
     lib.tsq_evolve.argtypes = [vp, vp, i64, vp, sz, vp]
+    lib.tsq_set_potential_td.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.tsq_evolve_td.argtypes = [vp, vp, i64, ctypes.POINTER(d), vp, sz, vp]
     lib.tsq_observables.argtypes = [vp, vp, vp, ctypes.POINTER(d), ctypes.POINTER(d), vp, sz, vp]
     vpp = ctypes.POINTER(vp)
     lib.tsq_batch_create.argtypes = [vpp, vpp, vpp, ctypes.POINTER(i64), i32,
@@ -158,6 +161,19 @@ def tsq_set_potential(plan: int, V_dev: int, ws: int, ws_bytes: int, stream: int
 
 def tsq_evolve(plan: int, psi_dev: int, steps: int, ws: int, ws_bytes: int, stream: int) -> None:
     _check(load_library().tsq_evolve(plan, psi_dev, int(steps), ws, ws_bytes, stream))
+
+
+def tsq_set_potential_td(plan: int, V0_dev: int, W_dev: int, ws: int, ws_bytes: int,
+                         stream: int) -> None:
+    _check(load_library().tsq_set_potential_td(plan, V0_dev, W_dev, ws, ws_bytes, stream))
+
+
+def tsq_evolve_td(plan: int, psi_dev: int, f, ws: int, ws_bytes: int, stream: int) -> None:
+    """`f`: the modulation of each step at its midpoint (len(f) steps)."""
+    import numpy as np
+    fv = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1))
+    ptr = fv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if fv.size else None
+    _check(load_library().tsq_evolve_td(plan, psi_dev, int(fv.size), ptr, ws, ws_bytes, stream))
 
 
 def tsq_observables(plan: int, psi_dev: int, V_dev: int, ws: int, ws_bytes: int,
@@ -275,6 +291,26 @@ class Plan:
                           _stream_handle(V.device))
         self._V = V
 
+    def set_potential_td(self, V0, W) -> None:
+        """Time-dependent potential V0 + f(t) W (modulations given to evolve_td)."""
+        torch = _torch()
+        for name, a in (("V0", V0), ("W", W)):
+            if a.dtype != torch.float64 or not a.is_contiguous() or tuple(a.shape) != (self.problem.ny, self.problem.nx):
+                raise ValueError(f"{name} must be a contiguous float64 (ny, nx) device tensor")
+        ws = self.workspace()
+        tsq_set_potential_td(self.handle, V0.data_ptr(), W.data_ptr(), ws.data_ptr(), ws.numel(),
+                             _stream_handle(V0.device))
+        self._V = None
+
+    def evolve_td(self, psi, f):
+        """Apply len(f) steps to psi in place, step n under V0 + f[n] W (f[n] taken
+        at the step's midpoint), and return it."""
+        self._check_psi(psi)
+        ws = self.workspace()
+        tsq_evolve_td(self.handle, psi.data_ptr(), f, ws.data_ptr(), ws.numel(),
+                      _stream_handle(psi.device))
+        return psi
+
     def _check_psi(self, psi) -> None:
         torch = _torch()
         want = torch.complex128 if self.dtype == "c128" else torch.complex64
@@ -374,6 +410,19 @@ def evolve(psi, V, dt: float, steps: int, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
     plan.set_schedule(steps_per_pass, segment_rows, pairs_per_lane, phase_store)
     plan.set_potential(V)
     plan.evolve(psi, steps)
+    return psi
+
+
+def evolve_td(psi, V0, W, f, dt: float, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
+              steps_per_pass: int = 0, segment_rows: int = 0, phase_store: int = 0):
+    """Evolve psi in place by len(f) steps under V(t) = V0 + f(t) W, step n using
+    f[n] = f(t_n + dt/2) (periodic mesh, order 2)."""
+    ny, nx = psi.shape
+    plan = Plan(nx, ny, dt, _dtype_name(psi), dx=dx, dy=dy, mass=mass, hbar=hbar,
+                device=psi.device)
+    plan.set_schedule(steps_per_pass, segment_rows, 1, phase_store)
+    plan.set_potential_td(V0, W)
+    plan.evolve_td(psi, f)
     return psi
 
 

@@ -1,0 +1,10 @@
+// March kernel instances: complex128, time-dependent potential variant.
+#include "tsq_march.hpp"
+
+namespace tsq {
+
+const void* march_ptr_c128_td(int steps, bool last, int ppl, bool lds) {
+    return pick_kernel<C128, Variant::TimeDep>(steps, last, ppl, lds);
+}
+
+}  // namespace tsq

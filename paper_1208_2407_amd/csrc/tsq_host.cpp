@@ -38,6 +38,7 @@ struct tsq_plan {
     size_t sites, elem, pelem;
     size_t off_psi2, off_ptab, off_scratch, ws_bytes;
     const void* ws_bound;
+    bool td;  // the bound workspace holds a time-dependent table (tsq_set_potential_td)
 };
 
 namespace {
@@ -110,26 +111,27 @@ int device_cus() {
     return g_dev.cus;
 }
 
-int occupancy_cached(int dtype, int steps, bool last, int ppl, bool lds, bool closed) {
-    // [dtype][steps][last][ppl][lds][closed]; 0 = not yet queried
-    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3][2][2];
+int occupancy_cached(int dtype, int steps, bool last, int ppl, bool lds, bool closed, bool td) {
+    // [dtype][steps][last][ppl][lds][closed][td]; 0 = not yet queried
+    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3][2][2][2];
     std::atomic<int>& slot =
-        table[dtype & 1][steps][last ? 1 : 0][ppl][lds ? 1 : 0][closed ? 1 : 0];
+        table[dtype & 1][steps][last ? 1 : 0][ppl][lds ? 1 : 0][closed ? 1 : 0][td ? 1 : 0];
     int v = slot.load(std::memory_order_relaxed);
     if (v == 0) {
-        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl, lds, false, closed);
+        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl, lds, false, closed, td);
         if (v <= 0) v = 1;
         slot.store(v, std::memory_order_relaxed);
     }
     return v;
 }
 
-int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl, bool lds, bool closed) {
+int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl, bool lds, bool closed,
+                     bool td) {
     const tsq::MarchGeometry g = tsq::march_geometry(p->p.nx, p->p.ny, steps, last, ppl, 2);
     int cus = device_cus();
     if (cus <= 0) cus = 256;
     const long long slots =
-        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl, lds, closed) *
+        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl, lds, closed, td) *
         tsq::kWavesPerBlock;
     const long long pairs = (p->p.ny + 1) / 2;
     long long segs = slots / g.nstrips;
@@ -368,6 +370,9 @@ int tsq_batch_create(tsq_plan* const* plans, void* const* psi, void* const* ws, 
                         "entry %d: the batched form runs periodic order-2 plans only", i);
         if (plans[i]->ws_bound != ws[i])
             return fail(TSQ_ERR_STATE, "entry %d: workspace is not the one given to tsq_set_potential", i);
+        if (plans[i]->td)
+            return fail(TSQ_ERR_UNSUPPORTED,
+                        "entry %d: the batched form runs time-independent potentials only", i);
         if (reinterpret_cast<uintptr_t>(psi[i]) % 16 != 0)
             return fail(TSQ_ERR_ARG, "entry %d: psi must be 16-byte aligned", i);
     }
@@ -579,6 +584,7 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
     p->off_scratch = end;
     p->ws_bytes = p->off_scratch + kScratchBytes;
     p->ws_bound = nullptr;
+    p->td = false;
     *out = p;
     return ok();
 }
@@ -630,7 +636,9 @@ int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int3
         return fail(TSQ_ERR_ARG, "order-4 evolution of %lld steps is too long for one call",
                     (long long)steps);
     std::vector<PassGroup> groups;
-    const bool cb = pass_groups(plan, steps, plan->sched.steps_per_pass, groups);
+    const int S = plan->td ? std::min(plan->sched.steps_per_pass, tsq::kMaxTdSteps)
+                           : plan->sched.steps_per_pass;
+    const bool cb = pass_groups(plan, steps, S, groups);
     int64_t n = 0;
     for (const PassGroup& x : groups) n += x.count;
     *passes = n;
@@ -652,10 +660,36 @@ int tsq_set_potential(tsq_plan* plan, const double* V, void* ws, size_t ws_bytes
             return fail(TSQ_ERR_DEVICE, "phase table launch: %s", hipGetErrorString(e));
     }
     plan->ws_bound = ws;
+    plan->td = false;
     return ok();
 }
 
-int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_bytes, void* stream) {
+int tsq_set_potential_td(tsq_plan* plan, const double* V0, const double* W, void* ws,
+                         size_t ws_bytes, void* stream) {
+    if (!plan || !V0 || !W) return fail(TSQ_ERR_ARG, "null plan or potential");
+    if (plan->p.order != 2)
+        return fail(TSQ_ERR_UNSUPPORTED, "time-dependent potentials run with order-2 plans only");
+    if (plan->p.bc != TSQ_BC_PERIODIC)
+        return fail(TSQ_ERR_UNSUPPORTED, "time-dependent potentials run on periodic meshes only");
+    int rc = check_ws(plan, ws, ws_bytes);
+    if (rc) return rc;
+    char* w = static_cast<char*>(ws);
+    hipError_t e = tsq::launch_td_table(V0, W, w + plan->kind[0].off_ptab, (long long)plan->sites,
+                                        plan->kind[0].dt, plan->eps0, plan->p.hbar,
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "table launch: %s", hipGetErrorString(e));
+    plan->ws_bound = ws;
+    plan->td = true;
+    return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checks shared by tsq_evolve and tsq_evolve_td.
+int check_evolve(const tsq_plan* plan, const void* psi, int64_t steps, const void* ws,
+                 size_t ws_bytes) {
     if (!plan || !psi) return fail(TSQ_ERR_ARG, "null plan or psi");
     if (steps < 0) return fail(TSQ_ERR_ARG, "steps must be >= 0 (%lld)", (long long)steps);
     if (reinterpret_cast<uintptr_t>(psi) % 16 != 0) return fail(TSQ_ERR_ARG, "psi must be 16-byte aligned");
@@ -664,18 +698,23 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
     if (plan->ws_bound == nullptr) return fail(TSQ_ERR_STATE, "tsq_set_potential has not been called");
     if (plan->ws_bound != ws)
         return fail(TSQ_ERR_STATE, "workspace differs from the one given to tsq_set_potential");
-    if (steps == 0) return ok();
-
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    char* w = static_cast<char*>(ws);
-    void* buf[2] = {psi, w + plan->off_psi2};
-    const int S = plan->sched.steps_per_pass;
-    const int ppl = plan->sched.pairs_per_lane;
-    const bool lds = plan->sched.phase_store == 2;
-
     if (plan->p.order == 4 && steps > 10000000LL)
         return fail(TSQ_ERR_ARG, "order-4 evolution of %lld steps is too long for one call",
                     (long long)steps);
+    return TSQ_OK;
+}
+
+// Launch the passes of `steps` steps (f: per-step modulation of a
+// time-dependent potential, else null) and the copy back if any.
+int run_evolution(tsq_plan* plan, void* psi, int64_t steps, void* ws, hipStream_t s,
+                  const double* f) {
+    char* w = static_cast<char*>(ws);
+    void* buf[2] = {psi, w + plan->off_psi2};
+    const bool td = f != nullptr;
+    const int S = td ? std::min(plan->sched.steps_per_pass, tsq::kMaxTdSteps)
+                     : plan->sched.steps_per_pass;
+    const int ppl = plan->sched.pairs_per_lane;
+    const bool lds = plan->sched.phase_store == 2;
     std::vector<PassGroup> groups;
     const bool copy_back = pass_groups(plan, steps, S, groups);
 
@@ -685,7 +724,8 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
     d.pairs_per_lane = ppl;
     d.phase_lds = lds;
     d.closed = plan->p.bc == TSQ_BC_CLOSED;
-    int64_t i = 0;
+    d.td = td;
+    int64_t i = 0, n0 = 0;  // pass index, first step of the pass
     for (const PassGroup& g : groups) {
         const SubStep& u = plan->kind[g.kind];
         d.ptab = w + u.off_ptab;
@@ -699,12 +739,14 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
             d.steps = g.size;
             d.first = g.opens && k == 0;
             d.last = g.closes && k + 1 == g.count;
+            d.f = td ? f + n0 : nullptr;
             d.seg_rows = plan->sched.segment_rows
                              ? plan->sched.segment_rows
-                             : default_seg_rows(plan, d.steps, d.last, ppl, lds, d.closed);
+                             : default_seg_rows(plan, d.steps, d.last, ppl, lds, d.closed, td);
             hipError_t e = tsq::launch_pass(plan->p.dtype, d, s);
             if (e != hipSuccess)
                 return fail(TSQ_ERR_DEVICE, "step pass launch: %s", hipGetErrorString(e));
+            n0 += g.size;
         }
     }
     if (copy_back) {
@@ -712,6 +754,34 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
         if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "copy back: %s", hipGetErrorString(e));
     }
     return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_evolve(plan, psi, steps, ws, ws_bytes);
+    if (rc) return rc;
+    if (plan->td)
+        return fail(TSQ_ERR_STATE, "the workspace holds a time-dependent potential: use tsq_evolve_td");
+    if (steps == 0) return ok();
+    return run_evolution(plan, psi, steps, ws, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int tsq_evolve_td(tsq_plan* plan, void* psi, int64_t steps, const double* f, void* ws,
+                  size_t ws_bytes, void* stream) {
+    int rc = check_evolve(plan, psi, steps, ws, ws_bytes);
+    if (rc) return rc;
+    if (!plan->td)
+        return fail(TSQ_ERR_STATE, "tsq_set_potential_td has not been called on this workspace");
+    if (steps > 0 && !f) return fail(TSQ_ERR_ARG, "null modulation array");
+    for (int64_t n = 0; n < steps; ++n)
+        if (!std::isfinite(f[n])) return fail(TSQ_ERR_ARG, "f[%lld] is not finite", (long long)n);
+    if (plan->sched.pairs_per_lane != 1)
+        return fail(TSQ_ERR_ARG, "time-dependent potentials run with 1 pair per lane");
+    if (steps == 0) return ok();
+    return run_evolution(plan, psi, steps, ws, static_cast<hipStream_t>(stream), f);
 }
 
 int tsq_observables(const tsq_plan* plan, const void* psi, const double* V, double* norm_out,

@@ -26,12 +26,15 @@ struct PassDesc {
     int pairs_per_lane;   // 1 or 2 x-pairs held by each lane
     bool phase_lds;       // phase ring in LDS (else registers)
     bool closed = false;  // hard walls instead of periodic wrap
+    bool td = false;      // time-dependent potential: the table holds (theta0, w)
+    const double* f = nullptr;  // td: modulation f_n of this pass's steps (host, `steps` values)
     Coef64 oxh, oyh;      // tau = dt/2 along x, y
     Coef64 ox2, oy2;      // tau = dt along x, y
 };
 
 constexpr int kMaxSteps = 8;     // deepest fusion (phase ring in LDS)
 constexpr int kMaxRegSteps = 4;  // deepest fusion with the phase ring in registers
+constexpr int kMaxTdSteps = 4;   // deepest fusion with a time-dependent potential
 constexpr int kWaveSize = 64;
 constexpr int kWavesPerBlock = 4;
 
@@ -58,6 +61,7 @@ struct MarchArgs {
     R o1xs, o1xd, o1ys, o1yd;  // odd factors opening the pass: tau = dt/2 (first pass) or dt
     R o2xs, o2xd, o2ys, o2yd;  // odd factors between steps, tau = dt
     R ehxs, ehxd, ehys, ehyd;  // even factors and the closing odd factors, tau = dt/2
+    double g[kMaxSteps];       // time-dependent potential: f_n of step k of the pass
 };
 
 template <class R>
@@ -77,6 +81,7 @@ MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
     a.o1xs = (R)ox1.s; a.o1xd = (R)ox1.d; a.o1ys = (R)oy1.s; a.o1yd = (R)oy1.d;
     a.o2xs = (R)d.ox2.s; a.o2xd = (R)d.ox2.d; a.o2ys = (R)d.oy2.s; a.o2yd = (R)d.oy2.d;
     a.ehxs = (R)d.oxh.s; a.ehxd = (R)d.oxh.d; a.ehys = (R)d.oyh.s; a.ehyd = (R)d.oyh.d;
+    for (int k = 0; k < kMaxSteps; ++k) a.g[k] = (d.td && d.f && k < d.steps) ? d.f[k] : 0.0;
     return a;
 }
 
@@ -91,13 +96,18 @@ struct BatchTile {
 // Resident blocks per compute unit of one march kernel instance (0 if the
 // query fails); used to size segments so a pass is one round of resident waves.
 int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
-                        bool batch = false, bool closed = false);
+                        bool batch = false, bool closed = false, bool td = false);
 bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
-                          bool closed = false);
+                          bool closed = false, bool td = false);
 
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long sites,
                               double dt, double eps0, double hbar, hipStream_t s);
+// Table of the time-dependent potential V0 + f(t) W: per site the phase angle
+// theta0 = dt (V0 + eps0) / hbar and its modulation w = dt W / hbar, as a
+// double2 (16 B/site, both dtypes); step n's phase is exp(-i (theta0 + f_n w)).
+hipError_t launch_td_table(const double* V0, const double* W, void* table, long long sites,
+                           double dt, double eps0, double hbar, hipStream_t s);
 hipError_t launch_pass(int dtype, const PassDesc& d, hipStream_t s);
 // Batched pass: `nwaves` wavefronts walk `ntiles` tiles of `jobs` (device
 // MarchArgs<double> for complex128, MarchArgs<float> for complex64).

@@ -17,13 +17,15 @@ const void* march_ptr_c128_batch(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c64_batch(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c128_closed(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c64_closed(int steps, bool last, int ppl, bool lds);
+const void* march_ptr_c128_td(int steps, bool last, int ppl, bool lds);
+const void* march_ptr_c64_td(int steps, bool last, int ppl, bool lds);
 
 namespace {
 
 struct C128 {};
 struct C64 {};
 
-enum class Variant { Single, Batch, Closed };
+enum class Variant { Single, Batch, Closed, TimeDep, None };
 
 const void* march_kernel_ptr(int dtype, int steps, bool last, int ppl, bool lds, Variant v) {
     const bool d = dtype == 1;
@@ -34,12 +36,18 @@ const void* march_kernel_ptr(int dtype, int steps, bool last, int ppl, bool lds,
             return d ? march_ptr_c128_batch(steps, last, ppl, lds) : march_ptr_c64_batch(steps, last, ppl, lds);
         case Variant::Closed:
             return d ? march_ptr_c128_closed(steps, last, ppl, lds) : march_ptr_c64_closed(steps, last, ppl, lds);
+        case Variant::TimeDep:
+            return d ? march_ptr_c128_td(steps, last, ppl, lds) : march_ptr_c64_td(steps, last, ppl, lds);
+        case Variant::None:
+            break;
     }
     return nullptr;
 }
 
-Variant variant_of(bool batch, bool closed) {
-    return batch ? Variant::Batch : (closed ? Variant::Closed : Variant::Single);
+Variant variant_of(bool batch, bool closed, bool td) {
+    if (batch) return Variant::Batch;
+    if (td) return closed ? Variant::None : Variant::TimeDep;  // no closed time-dependent march
+    return closed ? Variant::Closed : Variant::Single;
 }
 
 // ------------------------------------------------------------------ phase table (row a0)
@@ -66,6 +74,16 @@ __global__ void phase_table_c64(const double* __restrict__ V, float4* __restrict
         float lr = (float)(c - (double)hr), li = (float)(-s - (double)hi);
         P[l] = make_float4(hr, hi, lr, li);
     }
+}
+
+// Time-dependent potential V0 + f(t) W: per site theta0 = dt (V0 + eps0) / hbar
+// and w = dt W / hbar; step n's phase is exp(-i (theta0 + f_n w)), formed in
+// the march.
+__global__ void td_table(const double* __restrict__ V0, const double* __restrict__ W,
+                         double2* __restrict__ T, long long n, double dt, double eps0, double hbar) {
+    for (long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x; l < n;
+         l += (long long)gridDim.x * blockDim.x)
+        T[l] = make_double2(dt * (V0[l] + eps0) / hbar, dt * W[l] / hbar);
 }
 
 // ------------------------------------------------------------------ observables (row a7)
@@ -190,16 +208,26 @@ hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long 
     return hipGetLastError();
 }
 
+hipError_t launch_td_table(const double* V0, const double* W, void* table, long long sites,
+                           double dt, double eps0, double hbar, hipStream_t s) {
+    const int threads = 256;
+    long long want = (sites + threads - 1) / threads;
+    const int blocks = (int)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(td_table, dim3(blocks), dim3(threads), 0, s, V0, W,
+                       reinterpret_cast<double2*>(table), sites, dt, eps0, hbar);
+    return hipGetLastError();
+}
+
 bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
-                          bool closed) {
+                          bool closed, bool td) {
     return march_kernel_ptr(dtype, steps, last, pairs_per_lane, phase_lds,
-                            variant_of(false, closed)) != nullptr;
+                            variant_of(false, closed, td)) != nullptr;
 }
 
 int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
-                        bool batch, bool closed) {
+                        bool batch, bool closed, bool td) {
     const void* f = march_kernel_ptr(dtype, steps, last, pairs_per_lane, phase_lds,
-                                     variant_of(batch, closed));
+                                     variant_of(batch, closed, td));
     if (!f) return 0;
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kWaveSize * kWavesPerBlock, 0) !=
@@ -222,7 +250,7 @@ hipError_t launch_batch(int dtype, int steps, bool last, int pairs_per_lane, boo
 
 hipError_t launch_pass(int dtype, const PassDesc& d, hipStream_t s) {
     const void* f = march_kernel_ptr(dtype, d.steps, d.last, d.pairs_per_lane, d.phase_lds,
-                                     variant_of(false, d.closed));
+                                     variant_of(false, d.closed, d.td));
     if (!f) return hipErrorInvalidValue;
     hipError_t e = dtype == 1 ? launch_with<double>(f, d, s) : launch_with<float>(f, d, s);
     if (e != hipSuccess) return e;

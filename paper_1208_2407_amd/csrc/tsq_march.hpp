@@ -96,6 +96,65 @@ __device__ __forceinline__ void apply_phase(float& re, float& im, const float4 p
     im = ni;
 }
 
+// ------------------------------------------------------------------ time-dependent phase
+
+// sin and cos of x in FP64 for the phase of a time-dependent potential,
+// written from the mathematics: Cody and Waite's additive reduction
+// r = x - k pi/2, with pi/2 split into C1 (the double nearest pi/2) and C2
+// (the double nearest pi/2 - C1) and the product k C1 exact inside an FMA;
+// the Taylor series of sin and cos on |r| <= pi/4 through r^17 and r^16 (the
+// first omitted terms are below 1e-19); the quadrant k mod 4.  A few ulp for
+// |x| < 2^40.
+__device__ __forceinline__ void sincos_td(double x, double& sn, double& cs) {
+    const double C1 = 0x1.921fb54442d18p+0;   // pi/2 rounded to double
+    const double C2 = 0x1.1a62633145c07p-54;  // pi/2 - C1 rounded to double
+    const double k = rint(x * 0x1.45f306dc9c883p-1);  // x * (2/pi)
+    double r = mad(-k, C1, x);
+    r = mad(-k, C2, r);
+    const double r2 = r * r;
+    // sin r = r + r^3 (-1/3! + r^2/5! - ... + r^14/17!)
+    double ps = 1.0 / 355687428096000.0;
+    ps = mad(ps, r2, -1.0 / 1307674368000.0);
+    ps = mad(ps, r2, 1.0 / 6227020800.0);
+    ps = mad(ps, r2, -1.0 / 39916800.0);
+    ps = mad(ps, r2, 1.0 / 362880.0);
+    ps = mad(ps, r2, -1.0 / 5040.0);
+    ps = mad(ps, r2, 1.0 / 120.0);
+    ps = mad(ps, r2, -1.0 / 6.0);
+    const double sr = mad(r * r2, ps, r);
+    // cos r = 1 + r^2 (-1/2! + r^2/4! - ... + r^14/16!)
+    double pc = 1.0 / 20922789888000.0;
+    pc = mad(pc, r2, -1.0 / 87178291200.0);
+    pc = mad(pc, r2, 1.0 / 479001600.0);
+    pc = mad(pc, r2, -1.0 / 3628800.0);
+    pc = mad(pc, r2, 1.0 / 40320.0);
+    pc = mad(pc, r2, -1.0 / 720.0);
+    pc = mad(pc, r2, 1.0 / 24.0);
+    pc = mad(pc, r2, -0.5);
+    const double cr = mad(r2, pc, 1.0);
+    // quadrant q: (sin, cos) of x = (sr, cr), (cr, -sr), (-sr, -cr), (-cr, sr)
+    const int q = (int)((long long)k & 3);
+    const double a = (q & 1) ? cr : sr;
+    const double b = (q & 1) ? sr : cr;
+    sn = (q & 2) ? -a : a;
+    cs = ((q + 1) & 2) ? -b : b;
+}
+
+// Potential phase of step n under V0 + f_n W: tw = (theta0, w) of the site,
+// g = f_n; the factor exp(-i (theta0 + g w)) is formed in FP64 and applied as
+// the static tables are (complex64: split into hi + lo floats).
+__device__ __forceinline__ void apply_phase_td(double& re, double& im, const double2 tw, double g) {
+    double sn, cs;
+    sincos_td(mad(g, tw.y, tw.x), sn, cs);
+    apply_phase(re, im, make_double2(cs, -sn));
+}
+__device__ __forceinline__ void apply_phase_td(float& re, float& im, const double2 tw, double g) {
+    double sn, cs;
+    sincos_td(mad(g, tw.y, tw.x), sn, cs);
+    const float hr = (float)cs, hi = (float)(-sn);
+    apply_phase(re, im, make_float4(hr, hi, (float)(cs - (double)hr), (float)(-sn - (double)hi)));
+}
+
 // ------------------------------------------------------------------ dtype traits
 
 struct C128 {
@@ -228,6 +287,12 @@ __device__ __forceinline__ void phase_row(Row<R, SPL>& w, const PT* p) {
     for (int i = 0; i < SPL; ++i) apply_phase(w.re[i], w.im[i], p[i]);
 }
 
+template <class R, int SPL>
+__device__ __forceinline__ void phase_row_td(Row<R, SPL>& w, const double2* p, double g) {
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) apply_phase_td(w.re[i], w.im[i], p[i], g);
+}
+
 // Calls f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
 template <class F, int... Is>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
@@ -277,9 +342,11 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // boundary of the two (o's G row and n's F row; n's G row gets the same
 // factors in stage k+1, where n is the older pair), then, for k < S, step
 // k+1's even factors and the potential phase on o.  Stage K-1 = S of the last pass applies only the
-// closing odd factors.  Closed meshes skip the y-pairs that cross a wall
+// closing odd factors.  With a time-dependent potential (TD) the phase pair
+// holds (theta0, w) per site and stage k forms step k's factor from a.g[k].
+// Closed meshes skip the y-pairs that cross a wall
 // (`qk` is the pair stage k completes; a wavefront-uniform test).
-template <int S, int K, bool CLOSED, class R, int SPL, class PT, class PhaseFn>
+template <int S, int K, bool CLOSED, bool TD, class R, int SPL, class PT, class PhaseFn>
 __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
                                                const MarchArgs<R>& a,
                                                const XPairs<SPL / 2, CLOSED>& xm, int qk, bool rev,
@@ -303,8 +370,13 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
         even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
         even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
         if (ey_ok) pair_y(o.f, o.g, a.ehys, a.ehyd);
-        phase_row(o.f, ph.f);
-        phase_row(o.g, ph.g);
+        if constexpr (TD) {
+            phase_row_td(o.f, ph.f, a.g[k]);
+            phase_row_td(o.g, ph.g, a.g[k]);
+        } else {
+            phase_row(o.f, ph.f);
+            phase_row(o.g, ph.g);
+        }
         if (ey_ok) pair_y(o.f, o.g, a.ehys, a.ehyd);
         even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
         even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
@@ -315,10 +387,10 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
 // registers (LDS = false) or, for stages 1..S-1, in a per-lane LDS ring
 // (LDS = true; stage 0 reads registers).
 // LDS ring of one wavefront: [slot][row][site][lane] phase factors.
-template <class T, int S, int PPL, bool LDS>
+template <class PT, int S, int PPL, bool LDS>
 struct WaveRing {
     static constexpr int kSlots = (LDS && S > 1) ? S - 1 : 1;
-    typename T::PT v[kSlots][2][2 * PPL][kWaveSize];
+    PT v[kSlots][2][2 * PPL][kWaveSize];
 };
 
 // Site-wise loads and stores for closed meshes (odd sides allowed, so rows
@@ -367,15 +439,18 @@ __device__ __forceinline__ PT zero_phase() {
 // by stage 0 in iteration j+1; register phases keep one home per psi home,
 // the LDS ring keeps two register homes (pairs j and j-1) and moves pair
 // j-1's phase to the ring at the end of iteration j.
-template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED>
+template <class T, bool TD>
+using PhaseT = std::conditional_t<TD, double2, typename T::PT>;
+
+template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD>
 __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, int strip, int seg,
-                                           bool rev, int lane, typename T::PT* ring) {
+                                           bool rev, int lane, PhaseT<T, TD>* ring) {
     using R = typename T::R;
-    using PT = typename T::PT;
+    using PT = PhaseT<T, TD>;
     constexpr int SPL = 2 * PPL;
     constexpr int K = S + (LAST ? 1 : 0);
     constexpr int HL = (K + PPL - 1) / PPL;
-    constexpr int NL = WaveRing<T, S, PPL, LDS>::kSlots;
+    constexpr int NL = WaveRing<PT, S, PPL, LDS>::kSlots;
     constexpr int NH = LDS ? ((K + 3) & ~1) : K + 2;  // even with the LDS ring
     constexpr int NP = LDS ? 2 : NH;                   // phase homes
     const int nx = a.nx, ny = a.ny;
@@ -526,7 +601,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         load_phase(ph[u % NP]);
         static_for<K>([&](auto KK) {
             constexpr int k = decltype(KK)::value;
-            pipeline_stage<S, K, CLOSED, R, SPL, PT>(
+            pipeline_stage<S, K, CLOSED, TD, R, SPL, PT>(
                 k, home[(u - 1 - k + 2 * NH) % NH], home[(u - k + 2 * NH) % NH], a, xm,
                 rev ? q + k : q - k, rev, [&](int kk) {
                     if (!LDS || kk == 0) return ph[(u - 1 - kk + 2 * NP) % NP];
@@ -565,10 +640,10 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
 }
 
 // One problem, one tile per wavefront.
-template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED>
+template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD>
 __global__ void __launch_bounds__(kWaveSize * kWavesPerBlock)
 march_kernel(const MarchArgs<typename T::R> a) {
-    __shared__ WaveRing<T, S, PPL, LDS> rings[LDS ? kWavesPerBlock : 1];
+    __shared__ WaveRing<PhaseT<T, TD>, S, PPL, LDS> rings[LDS ? kWavesPerBlock : 1];
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
     // XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
@@ -582,8 +657,8 @@ march_kernel(const MarchArgs<typename T::R> a) {
     if (tile >= (long long)a.nstrips * a.nsegs) return;  // uniform per wavefront
     const int strip = (int)(tile / a.nsegs);
     const int seg = (int)(tile - (long long)strip * a.nsegs);
-    march_tile<T, S, LAST, PPL, LDS, CLOSED>(a, strip, seg, seg & 1, lane,
-                                             &rings[LDS ? wave : 0].v[0][0][0][lane]);
+    march_tile<T, S, LAST, PPL, LDS, CLOSED, TD>(a, strip, seg, seg & 1, lane,
+                                                 &rings[LDS ? wave : 0].v[0][0][0][lane]);
 }
 
 // Many problems: a fixed grid of wavefronts walks a work list of tiles
@@ -593,33 +668,37 @@ template <class T, int S, bool LAST, int PPL, bool LDS>
 __global__ void __launch_bounds__(kWaveSize * kWavesPerBlock)
 march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
                    const BatchTile* __restrict__ tiles, int ntiles) {
-    __shared__ WaveRing<T, S, PPL, LDS> rings[LDS ? kWavesPerBlock : 1];
+    __shared__ WaveRing<typename T::PT, S, PPL, LDS> rings[LDS ? kWavesPerBlock : 1];
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
     const int nw = gridDim.x * kWavesPerBlock;
     for (int i = blockIdx.x * kWavesPerBlock + wave; i < ntiles; i += nw) {
         const BatchTile t = tiles[i];
         const MarchArgs<typename T::R> a = jobs[t.job];
-        march_tile<T, S, LAST, PPL, LDS, false>(a, t.strip, t.seg, t.seg & 1, lane,
-                                                &rings[LDS ? wave : 0].v[0][0][0][lane]);
+        march_tile<T, S, LAST, PPL, LDS, false, false>(a, t.strip, t.seg, t.seg & 1, lane,
+                                                       &rings[LDS ? wave : 0].v[0][0][0][lane]);
     }
 }
 
 // Instances: periodic register ring for 1..4 steps per pass (1 or 2 pairs
 // per lane), periodic LDS ring for 1..kMaxSteps (1 pair per lane), single
-// and batched; closed meshes: both rings with 1 pair per lane, single only.
-enum class Variant { Single, Batch, Closed };
+// and batched; closed meshes: both rings with 1 pair per lane, single only;
+// time-dependent potentials (periodic): both rings, 1 pair per lane, at most
+// kMaxTdSteps steps per pass, single only.
+enum class Variant { Single, Batch, Closed, TimeDep };
 
 template <class T, int S, bool LAST, int PPL, bool LDS, Variant V>
 const void* kernel_ptr() {
     if constexpr (V == Variant::Single)
-        return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, false>);
+        return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, false, false>);
     else if constexpr (V == Variant::Batch)
         return reinterpret_cast<const void*>(&march_batch_kernel<T, S, LAST, PPL, LDS>);
-    else if constexpr (PPL == 1)
-        return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, true>);
-    else
+    else if constexpr (PPL != 1)
         return nullptr;
+    else if constexpr (V == Variant::Closed)
+        return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, true, false>);
+    else
+        return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, false, true>);
 }
 
 template <class T, Variant V, bool LAST, int PPL, bool LDS, int... Ss>
@@ -633,10 +712,14 @@ template <class T, Variant V, bool LAST>
 const void* pick_variant(int steps, int ppl, bool lds) {
     if (lds) {
         if (ppl != 1) return nullptr;
+        // the time-dependent march evaluates a sine and cosine per site and
+        // step; beyond 4 steps per pass its loop outgrows the instruction cache
+        if constexpr (V == Variant::TimeDep)
+            return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxTdSteps>());
         return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxSteps>());
     }
     if (ppl == 2) {
-        if constexpr (V == Variant::Closed) return nullptr;
+        if constexpr (V == Variant::Closed || V == Variant::TimeDep) return nullptr;
         return pick_steps<T, V, LAST, 2, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
     }
     return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());

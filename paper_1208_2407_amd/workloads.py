@@ -236,6 +236,27 @@ def potential(p: Problem, device="cpu", rows: Optional[Tuple[int, int]] = None,
     return out
 
 
+# Time-dependent potential V(t) = V0 + f(t) W: the static potential of a
+# problem plus a standing wave along x whose strength oscillates in time (a
+# "shaken" lattice), periodic on the mesh.
+
+def standing_wave(p: Problem, periods: int = 4, device="cpu",
+                  rows: Optional[Tuple[int, int]] = None,
+                  cols: Optional[Tuple[int, int]] = None) -> torch.Tensor:
+    """W(x, y) = cos(2 pi periods i / nx) at column i, on rows [r0, r1) x cols [c0, c1)."""
+    r0, r1 = rows if rows is not None else (0, p.ny)
+    c0, c1 = cols if cols is not None else (0, p.nx)
+    wx = torch.from_numpy(np.cos(2.0 * math.pi * periods * np.arange(c0, c1) / p.nx)).to(device)
+    return wx[None, :].expand(r1 - r0, c1 - c0).contiguous()
+
+
+def drive(dt: float, steps: int, amplitude: float = 0.2, omega: float = 0.5,
+          phase: float = 0.0, t0: float = 0.0) -> np.ndarray:
+    """f(t) = amplitude sin(omega t + phase) at the step midpoints t0 + (n + 1/2) dt."""
+    t = t0 + (np.arange(steps) + 0.5) * dt
+    return amplitude * np.sin(omega * t + phase)
+
+
 def random_state(nx: int, ny: int, seed: int) -> np.ndarray:
     """Unit-norm complex Gaussian noise: a state with every wavenumber present."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version():
-    assert tsq.tsq_abi_version() == 2
+    assert tsq.tsq_abi_version() == 3
 
 
 def problem(**kw):
@@ -110,6 +110,24 @@ def test_calls_reject_null_and_out_of_order_before_any_launch():
         assert lib.tsq_observables(h, None, 16, ctypes.byref(n), ctypes.byref(e), 256, 1 << 30, None) == -1
         assert lib.tsq_workspace_size(None, None) == -1
         assert lib.tsq_plan_destroy(None) == 0
+        # time-dependent potential: same checks, and it needs its own table
+        f = (ctypes.c_double * 2)(0.1, 0.2)
+        assert lib.tsq_set_potential_td(h, None, 16, 256, 1 << 30, None) == -1
+        assert lib.tsq_set_potential_td(h, 16, None, 256, 1 << 30, None) == -1
+        assert lib.tsq_set_potential_td(h, 16, 16, 256, 16, None) == -4
+        assert lib.tsq_evolve_td(h, None, 2, f, 256, 1 << 30, None) == -1
+        assert lib.tsq_evolve_td(h, 16, -1, f, 256, 1 << 30, None) == -1
+        assert lib.tsq_evolve_td(h, 16, 2, f, 256, 1 << 30, None) == -6  # no table set
+    finally:
+        tsq.tsq_plan_destroy(h)
+
+
+@pytest.mark.parametrize("kw", [dict(order=4), dict(bc=1, nx=63)])
+def test_time_dependent_potential_needs_periodic_order2(kw):
+    lib = tsq.load_library()
+    h = tsq.tsq_plan_create(problem(**kw))
+    try:
+        assert lib.tsq_set_potential_td(h, 16, 16, 256, 1 << 30, None) == -7
     finally:
         tsq.tsq_plan_destroy(h)
 

@@ -1,0 +1,171 @@
+"""GPU parity of the time-dependent potential V(t) = V0 + f(t) W against the
+FP64 oracle (each step frozen at its midpoint; the oracle's pins are in
+test_oracle_pins.py).  Tolerances as for the static path: complex128 <= 1e-12,
+complex64 <= 1e-5 relative L2."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1208_2407_amd as tsq
+from paper_1208_2407_amd import workloads as wl
+from tests.gpu_helpers import TOL, TORCH_DT, as_input, gpu_evolve, log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+ANISO = dict(dx=1.3, dy=0.8, mass=1.7, hbar=0.9)
+
+
+def setup_module(_):
+    oracle.build(force=False)
+    tsq.load_library()
+
+
+def gpu_evolve_td(psi0, V0, W, f, dt, dtype, steps_per_pass=0, segment_rows=0, phase_store=0,
+                  chunks=1, **consts):
+    ny, nx = psi0.shape
+    psi = torch.from_numpy(np.ascontiguousarray(psi0)).to(TORCH_DT[dtype]).cuda()
+    plan = tsq.Plan(nx, ny, dt, dtype, device=psi.device, **consts)
+    plan.set_schedule(steps_per_pass, segment_rows, 1, phase_store)
+    plan.set_potential_td(torch.from_numpy(np.ascontiguousarray(V0, dtype=np.float64)).cuda(),
+                          torch.from_numpy(np.ascontiguousarray(W, dtype=np.float64)).cuda())
+    for part in np.array_split(np.asarray(f, dtype=np.float64), chunks):
+        plan.evolve_td(psi, part)
+    torch.cuda.synchronize()
+    return psi.cpu().numpy().astype(np.complex128)
+
+
+SHAPES = [(2, 2), (4, 6), (130, 66), (258, 300), (66, 1030)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("S", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_td_ragged_meshes(shape, S, dtype):
+    nx, ny = shape
+    psi0 = wl.random_state(nx, ny, 17 + nx)
+    V0 = wl.random_potential(nx, ny, 18 + ny, scale=0.5)
+    W = wl.random_potential(nx, ny, 19 + nx, scale=0.7)
+    for steps in (1, 7, 2 * S + 1):
+        f = np.random.default_rng(steps).uniform(-1.5, 1.5, steps)
+        want = oracle.evolve_td(as_input(psi0, dtype), V0, W, f, 0.11, **ANISO)
+        for store in (1, 2):
+            got = gpu_evolve_td(psi0, V0, W, f, 0.11, dtype, steps_per_pass=S, segment_rows=16,
+                                phase_store=store, **ANISO)
+            err = rel_l2(got, want)
+            assert err <= TOL[dtype], (shape, S, store, steps, err)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_schedule_and_call_split_do_not_change_a_bit(dtype):
+    """Every schedule gives the same bits (a schedule deeper than the
+    time-dependent march fuses runs 4).  Splitting the modulation over several
+    calls continues the evolution: each call closes and reopens the odd half
+    factors that one call merges, so the split agrees to rounding."""
+    nx, ny = 258, 130
+    psi0 = wl.random_state(nx, ny, 3)
+    V0 = wl.random_potential(nx, ny, 4)
+    W = wl.random_potential(nx, ny, 5)
+    f = np.random.default_rng(6).uniform(-1, 1, 13)
+    ref = gpu_evolve_td(psi0, V0, W, f, 0.09, dtype, steps_per_pass=1, segment_rows=2, phase_store=1)
+    for S in range(1, 9):
+        for seg in (2, 6, 0):
+            for store in ((1, 2) if S <= 4 else (2,)):
+                got = gpu_evolve_td(psi0, V0, W, f, 0.09, dtype, steps_per_pass=S, segment_rows=seg,
+                                    phase_store=store)
+                assert np.array_equal(got, ref), (S, seg, store)
+    split = gpu_evolve_td(psi0, V0, W, f, 0.09, dtype, chunks=4)
+    assert rel_l2(split, ref) <= (1e-14 if dtype == "c128" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_constant_modulation_equals_static_potential(dtype):
+    """f_n = c for every step is the static potential V0 + c W: the in-kernel FP64
+    phase (sine and cosine written for the march) against the table of the static
+    path (the HIP math library's sincos)."""
+    nx, ny = 256, 192
+    psi0 = wl.random_state(nx, ny, 8)
+    V0 = wl.random_potential(nx, ny, 9, scale=3.0)
+    W = wl.random_potential(nx, ny, 10, scale=2.0)
+    c = 0.73
+    got = gpu_evolve_td(psi0, V0, W, np.full(40, c), 0.2, dtype, **ANISO)
+    want = gpu_evolve(psi0, V0 + c * W, 0.2, 40, dtype, **ANISO)
+    err = rel_l2(got, want)
+    log(f"  td constant f vs static {dtype}: {err:.3e}")
+    assert err <= (1e-13 if dtype == "c128" else 2e-6)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_large_phases(dtype):
+    """Phase angles of a few hundred radians per step (the range reduction of the
+    in-kernel sine and cosine; an FP64 angle of size a carries a rounding of
+    about a * 1e-16 whoever computes it, which bounds the sizes a 1e-12 parity
+    can be asked at)."""
+    nx, ny = 128, 96
+    psi0 = wl.random_state(nx, ny, 11)
+    V0 = wl.random_potential(nx, ny, 12, scale=300.0)
+    W = wl.random_potential(nx, ny, 13, scale=100.0)
+    f = np.random.default_rng(14).uniform(-2, 2, 9)
+    want = oracle.evolve_td(as_input(psi0, dtype), V0, W, f, 0.3)
+    got = gpu_evolve_td(psi0, V0, W, f, 0.3, dtype)
+    err = rel_l2(got, want)
+    log(f"  td large phases {dtype}: {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_forward_then_backward(dtype):
+    p = wl.packets_and_bumps(512, 384, 21, 0.05, 150, dtype)
+    psi0 = as_input(wl.initial_state(p).numpy(), dtype)
+    V0 = wl.potential(p).numpy()
+    W = wl.standing_wave(p).numpy()
+    f = wl.drive(p.dt, p.steps)
+    fwd = gpu_evolve_td(psi0, V0, W, f, p.dt, dtype)
+    back = gpu_evolve_td(fwd, V0, W, f[::-1], -p.dt, dtype)
+    err = rel_l2(back, psi0)
+    log(f"  td forward/backward {dtype}: {err:.3e}")
+    assert err <= (1e-13 if dtype == "c128" else 5e-6)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_driven_mesh_1024(dtype):
+    """1024^2 packets and bumps under the shaken standing wave, 200 steps, against
+    one oracle run; norm stays put."""
+    p = wl.packets_and_bumps(1024, 1024, 22, 0.05, 200, dtype)
+    psi0 = as_input(wl.initial_state(p).numpy(), dtype)
+    V0 = wl.potential(p).numpy()
+    W = wl.standing_wave(p).numpy()
+    f = wl.drive(p.dt, p.steps)
+    got = gpu_evolve_td(psi0, V0, W, f, p.dt, dtype)
+    want = oracle.evolve_td(psi0, V0, W, f, p.dt)
+    err = rel_l2(got, want)
+    n0, n1 = np.sum(np.abs(psi0) ** 2), np.sum(np.abs(got) ** 2)
+    log(f"  td driven 1024^2 {dtype}: rel L2 {err:.3e}, norm drift {n1 - n0:.3e}")
+    assert err <= TOL[dtype]
+
+
+def test_td_state_errors():
+    nx, ny = 64, 32
+    plan = tsq.Plan(nx, ny, 0.1, "c128")
+    psi = torch.zeros((ny, nx), dtype=torch.complex128, device="cuda")
+    V = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    plan.set_potential(V)
+    with pytest.raises(tsq.TsqError) as ei:
+        plan.evolve_td(psi, [0.1])
+    assert ei.value.status == -6
+    plan.set_potential_td(V, V)
+    with pytest.raises(tsq.TsqError) as ei:
+        plan.evolve(psi, 1)
+    assert ei.value.status == -6
+    with pytest.raises(tsq.TsqError) as ei:
+        plan.evolve_td(psi, [0.1, float("nan")])
+    assert ei.value.status == -1
+    with pytest.raises(tsq.TsqError) as ei:
+        tsq.Batch([plan], [psi], [3])
+    assert ei.value.status == -7
+    plan.set_schedule(2, 0, 2, 1)
+    with pytest.raises(tsq.TsqError) as ei:
+        plan.evolve_td(psi, [0.1])
+    assert ei.value.status == -1
+    plan.set_schedule(8, 0, 1, 2)
+    assert plan.passes(8) == (2, False)   # runs 4 steps per pass
