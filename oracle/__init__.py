@@ -51,6 +51,11 @@ def load_library(path: str):
     lib.tso_evolve.restype = i
     lib.tso_evolve_td.argtypes = [i, i, i, d, d, d, d, d, p, p, p, p, ll]
     lib.tso_evolve_td.restype = i
+    lib.tso_evolve3.argtypes = [i, i, i, i, d, d, d, d, d, d, p, p, ll]
+    lib.tso_evolve3.restype = i
+    lib.tso_observables3.argtypes = [i, i, i, i, d, d, d, d, d, p, p,
+                                     ctypes.POINTER(d), ctypes.POINTER(d)]
+    lib.tso_observables3.restype = i
     lib.tso_apply_factor.argtypes = [i, i, i, d, d, d, d, i, i, d, p, p]
     lib.tso_apply_factor.restype = i
     lib.tso_observables.argtypes = [i, i, i, d, d, d, d, p, p,
@@ -122,6 +127,38 @@ def evolve_td(psi0, V0, W, f, dt, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return psi
+
+
+def _as_psi3(psi) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    if a.ndim != 3:
+        raise ValueError("psi must be (nz, ny, nx)")
+    return a.copy()
+
+
+def evolve3(psi0, V, dt, steps, *, dx=1.0, dy=1.0, dz=1.0, mass=1.0, hbar=1.0,
+            bc="periodic") -> np.ndarray:
+    """Three-dimensional mesh (nz, ny, nx): `steps` second-order steps."""
+    psi = _as_psi3(psi0)
+    v = _as_v(V, psi.shape)
+    nz, ny, nx = psi.shape
+    rc = _load().tso_evolve3(nx, ny, nz, BC[bc], dx, dy, dz, mass, hbar, dt, v.ctypes.data,
+                             psi.ctypes.data, int(steps))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return psi
+
+
+def observables3(psi, V, *, dx=1.0, dy=1.0, dz=1.0, mass=1.0, hbar=1.0, bc="periodic"):
+    a = np.ascontiguousarray(np.asarray(psi, dtype=np.complex128))
+    v = _as_v(V, a.shape)
+    nz, ny, nx = a.shape
+    n, e = ctypes.c_double(), ctypes.c_double()
+    rc = _load().tso_observables3(nx, ny, nz, BC[bc], dx, dy, dz, mass, hbar, v.ctypes.data,
+                                  a.ctypes.data, ctypes.byref(n), ctypes.byref(e))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return n.value, e.value
 
 
 def apply_factor(psi0, V, which, parity, tau, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,

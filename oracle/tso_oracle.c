@@ -233,6 +233,130 @@ int tso_evolve_td(int nx, int ny, int bc, double dx, double dy, double mass, dou
     return 0;
 }
 
+/* ---- three dimensions ------------------------------------------------- */
+/*
+ * The extension to three-dimensional meshes that the paper names as future
+ * work (Sec. 5): the same split with a third axis, i.e. seven parts, the
+ * diagonal and the even and odd pairs along x, y and z.  One step, in the
+ * order the factors are applied:
+ *     Ox(h) Oy(h) Oz(h) Ex(h) Ey(h) Ez(h) P(dt) Ez(h) Ey(h) Ex(h) Oz(h) Oy(h) Ox(h)
+ * with eps_l = V_l + hbar^2/(m dx^2) + hbar^2/(m dy^2) + hbar^2/(m dz^2).
+ * Layout (nz, ny, nx), x fastest.
+ */
+
+static void sweep3(int nx, int ny, int nz, int bc, int axis, int parity, double s, double d,
+                   double *psi) {
+    int L = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)nx : (size_t)nx * (size_t)ny);
+    /* every line along `axis`: the other two coordinates */
+    long long lines = (long long)nx * ny * nz / L;
+    long long q;
+#pragma omp parallel for schedule(static)
+    for (q = 0; q < lines; ++q) {
+        size_t base;
+        if (axis == 0) {
+            base = (size_t)q * (size_t)nx;                       /* (z, y) rows */
+        } else if (axis == 1) {
+            long long z = q / nx, x = q % nx;                    /* (z, x) columns */
+            base = (size_t)z * (size_t)nx * (size_t)ny + (size_t)x;
+        } else {
+            base = (size_t)q;                                    /* (y, x) columns */
+        }
+        for (int j = parity; j < L; j += 2) {
+            int k = j + 1;
+            if (k == L) {
+                if (bc == TSO_BC_CLOSED) continue;
+                k = 0;
+            }
+            rotate(psi + 2 * (base + (size_t)j * stride), psi + 2 * (base + (size_t)k * stride), s, d);
+        }
+    }
+}
+
+/* Evolve psi (nz, ny, nx) in place by `steps` second-order steps; sides >= 2,
+ * even under periodic boundaries.  Returns 0, or -1 on a bad argument. */
+int tso_evolve3(int nx, int ny, int nz, int bc, double dx, double dy, double dz, double mass,
+                double hbar, double dt, const double *V, double *psi, long long steps) {
+    if (!sides_ok(nx, ny, bc) || !sides_ok(nz, 2, bc) || !params_ok(dx, dy, mass, hbar) ||
+        !(isfinite(dz) && dz > 0) || !isfinite(dt) || steps < 0 || V == NULL || psi == NULL)
+        return -1;
+    double h = 0.5 * dt;
+    double J[3] = {hbar * hbar / (2.0 * mass * dx * dx), hbar * hbar / (2.0 * mass * dy * dy),
+                   hbar * hbar / (2.0 * mass * dz * dz)};
+    double eps0 = 2.0 * (J[0] + J[1] + J[2]);
+    double sa[3], da[3];
+    for (int a = 0; a < 3; ++a) block_coeffs(h, J[a], hbar, &sa[a], &da[a]);
+    for (long long n = 0; n < steps; ++n) {
+        for (int a = 0; a < 3; ++a) sweep3(nx, ny, nz, bc, a, 1, sa[a], da[a], psi);  /* O(h) */
+        for (int a = 0; a < 3; ++a) sweep3(nx, ny, nz, bc, a, 0, sa[a], da[a], psi);  /* E(h) */
+        potential_phase(nx, ny * nz, dt, eps0, hbar, V, psi);
+        for (int a = 2; a >= 0; --a) sweep3(nx, ny, nz, bc, a, 0, sa[a], da[a], psi); /* E(h) */
+        for (int a = 2; a >= 0; --a) sweep3(nx, ny, nz, bc, a, 1, sa[a], da[a], psi); /* O(h) */
+    }
+    return 0;
+}
+
+/* Norm and energy <psi|H|psi>/N on a (nz, ny, nx) mesh, six neighbours
+ * (wrapping periodically, absent beyond closed walls); plane partial sums in
+ * plane order. */
+int tso_observables3(int nx, int ny, int nz, int bc, double dx, double dy, double dz,
+                     double mass, double hbar, const double *V, const double *psi,
+                     double *norm_out, double *energy_out) {
+    if (!sides_ok(nx, ny, bc) || !sides_ok(nz, 2, bc) || !params_ok(dx, dy, mass, hbar) ||
+        !(isfinite(dz) && dz > 0) || V == NULL || psi == NULL || norm_out == NULL ||
+        energy_out == NULL)
+        return -1;
+    double J[3] = {hbar * hbar / (2.0 * mass * dx * dx), hbar * hbar / (2.0 * mass * dy * dy),
+                   hbar * hbar / (2.0 * mass * dz * dz)};
+    double eps0 = 2.0 * (J[0] + J[1] + J[2]);
+    int n3[3] = {nx, ny, nz};
+    double *pn = (double *)calloc((size_t)nz, sizeof(double));
+    double *pe = (double *)calloc((size_t)nz, sizeof(double));
+    if (!pn || !pe) {
+        free(pn);
+        free(pe);
+        return -1;
+    }
+    int z;
+#pragma omp parallel for schedule(static)
+    for (z = 0; z < nz; ++z) {
+        double sn = 0.0, se = 0.0;
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int c[3] = {x, y, z};
+                size_t l = ((size_t)z * ny + y) * nx + x;
+                double pr = psi[2 * l], pi = psi[2 * l + 1];
+                double hr = (V[l] + eps0) * pr, hi = (V[l] + eps0) * pi;
+                for (int a = 0; a < 3; ++a)
+                    for (int dir = -1; dir <= 1; dir += 2) {
+                        int cc[3] = {c[0], c[1], c[2]};
+                        cc[a] += dir;
+                        if (cc[a] < 0 || cc[a] >= n3[a]) {
+                            if (bc == TSO_BC_CLOSED) continue;
+                            cc[a] = (cc[a] + n3[a]) % n3[a];
+                        }
+                        size_t m = ((size_t)cc[2] * ny + cc[1]) * nx + cc[0];
+                        hr -= J[a] * psi[2 * m];
+                        hi -= J[a] * psi[2 * m + 1];
+                    }
+                sn += pr * pr + pi * pi;
+                se += pr * hr + pi * hi;
+            }
+        pn[z] = sn;
+        pe[z] = se;
+    }
+    double n = 0.0, e = 0.0;
+    for (z = 0; z < nz; ++z) {
+        n += pn[z];
+        e += pe[z];
+    }
+    free(pn);
+    free(pe);
+    *norm_out = n;
+    *energy_out = (n > 0.0) ? e / n : 0.0;
+    return 0;
+}
+
 /* Apply one single factor, for tests of the operator structure:
  *   which = 0: Kx(parity, tau)   1: Ky(parity, tau)   2: P(tau) */
 int tso_apply_factor(int nx, int ny, int bc, double dx, double dy, double mass, double hbar,

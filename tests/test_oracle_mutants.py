@@ -31,6 +31,12 @@ MUTANTS = {
     "time-dependent modulation ignored": [("Vn[l] = V0[l] + f[n] * W[l];", "Vn[l] = V0[l] + 0.0 * W[l];")],
     "modulation lags one step": [("Vn[l] = V0[l] + f[n] * W[l];", "Vn[l] = V0[l] + f[n > 0 ? n - 1 : 0] * W[l];")],
     "modulation without the time step": [("Vn[l] = V0[l] + f[n] * W[l];", "Vn[l] = V0[l] + f[n] * W[l] / dt;")],
+    "3D: the z spacing takes the y one": [("hbar * hbar / (2.0 * mass * dz * dz)};\n    double eps0 = 2.0 * (J[0] + J[1] + J[2]);\n    double sa[3]",
+                                           "hbar * hbar / (2.0 * mass * dy * dy)};\n    double eps0 = 2.0 * (J[0] + J[1] + J[2]);\n    double sa[3]")],
+    "3D: diagonal misses the z constant": [("double eps0 = 2.0 * (J[0] + J[1] + J[2]);\n    double sa[3]",
+                                            "double eps0 = 2.0 * (J[0] + J[1]);\n    double sa[3]")],
+    "3D: opening odd z factor missing": [("for (int a = 0; a < 3; ++a) sweep3(nx, ny, nz, bc, a, 1, sa[a], da[a], psi);  /* O(h) */",
+                                          "for (int a = 0; a < 2; ++a) sweep3(nx, ny, nz, bc, a, 1, sa[a], da[a], psi);  /* O(h) */")],
     "energy misses y neighbours": [("hr -= Jy * psi[2 * m];", "hr -= 0.0 * psi[2 * m];"),
                                    ("hi -= Jy * psi[2 * m + 1];", "hi -= 0.0 * psi[2 * m + 1];")],
 }
@@ -47,6 +53,8 @@ CHECKS = [
     lambda: pins.test_energy_equals_dense_expectation((6, 4), "periodic"),
     lambda: pins.test_td_error_shrinks_as_dt_squared((6, 4), "periodic"),
     lambda: pins.test_td_step_equals_dense_product_of_frozen_steps(),
+    lambda: pins.test_3d_step_equals_dense_factor_product((4, 4, 4), "periodic"),
+    lambda: pins.test_3d_separable_problem_is_tensor_product_of_1d_runs(),
 ]
 
 

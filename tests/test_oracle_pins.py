@@ -382,3 +382,99 @@ def test_td_rejects_bad_arguments():
         oracle.evolve_td(psi, V, V, [0.0, np.nan], 0.1)
     with pytest.raises(ValueError):
         oracle.evolve_td(psi, V, np.zeros((4, 5)), [0.0], 0.1)
+
+
+# ---------------------------------------------------------------- three dimensions
+# The seven-part split of a 3D mesh (the extension Sec. 5 names).
+
+ANISO3 = dict(dx=1.3, dy=0.8, dz=1.1, mass=1.7, hbar=0.9)
+
+
+def _rand3(n3, seed):
+    nx, ny, nz = n3
+    rng = np.random.default_rng(seed)
+    psi = rng.standard_normal((nz, ny, nx)) + 1j * rng.standard_normal((nz, ny, nx))
+    return psi / np.linalg.norm(psi), rng.standard_normal((nz, ny, nx))
+
+
+@pytest.mark.parametrize("n3,bc", [((4, 4, 4), "periodic"), ((6, 4, 2), "periodic"),
+                                   ((2, 4, 6), "periodic"), ((5, 3, 3), "closed")])
+def test_3d_step_equals_dense_factor_product(n3, bc):
+    psi, V = _rand3(n3, 81)
+    dt, N = 0.23, 4
+    got = oracle.evolve3(psi, V, dt, N, bc=bc, **ANISO3)
+    U = np.linalg.matrix_power(dense.u2_dense3(n3, V, dt, bc=bc, **ANISO3), N)
+    assert rel(got, (U @ psi.reshape(-1)).reshape(psi.shape)) < 1e-13
+
+
+def test_3d_error_shrinks_as_dt_squared():
+    n3 = (4, 4, 4)
+    psi, V = _rand3(n3, 82)
+    H = dense.full_h3(n3, V, **ANISO3)
+    w, Q = np.linalg.eigh(H)
+    t = 1.0
+    exact = ((Q * np.exp(-1j * w * t / ANISO3["hbar"])) @ Q.conj().T @ psi.reshape(-1)).reshape(psi.shape)
+    errs = [rel(oracle.evolve3(psi, V, t / N, N, **ANISO3), exact) for N in (8, 16, 32, 64)]
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    for r in ratios:
+        assert abs(r - 4.0) < 0.1, (errs, ratios)
+
+
+def test_3d_separable_problem_is_tensor_product_of_1d_runs():
+    """V = Vx(x) + Vy(y) + Vz(z) and psi0 = f(x) g(y) h(z): every factor acts on one
+    axis, so N steps are the tensor product of three 1D second-order runs."""
+    nx, ny, nz = 12, 10, 8
+    rng = np.random.default_rng(83)
+    vx, vy, vz = (rng.standard_normal(n) for n in (nx, ny, nz))
+    f, g, h = (rng.standard_normal(n) + 1j * rng.standard_normal(n) for n in (nx, ny, nz))
+    V = vz[:, None, None] + vy[None, :, None] + vx[None, None, :]
+    psi = h[:, None, None] * g[None, :, None] * f[None, None, :]
+    dt, N = 0.17, 9
+    got = oracle.evolve3(psi, V, dt, N, **ANISO3)
+    k = dict(mass=ANISO3["mass"], hbar=ANISO3["hbar"])
+    fx = np.linalg.matrix_power(dense.u2_dense1(nx, vx, dt, d=ANISO3["dx"], **k), N) @ f
+    gy = np.linalg.matrix_power(dense.u2_dense1(ny, vy, dt, d=ANISO3["dy"], **k), N) @ g
+    hz = np.linalg.matrix_power(dense.u2_dense1(nz, vz, dt, d=ANISO3["dz"], **k), N) @ h
+    want = hz[:, None, None] * gy[None, :, None] * fx[None, None, :]
+    assert rel(got, want) < 1e-13
+
+
+def test_3d_z_uniform_problem_reduces_to_the_2d_evolution():
+    """A state and potential constant along z: the z factors and the z part of the
+    diagonal constant cancel (each z rotation of equal partners is exp(+i alpha)),
+    so every plane evolves as the 2D mesh does."""
+    nx, ny, nz = 16, 12, 6
+    psi2 = wl.random_state(nx, ny, 84)
+    V2 = wl.random_potential(nx, ny, 85)
+    psi = np.repeat(psi2[None], nz, axis=0)
+    V = np.repeat(V2[None], nz, axis=0)
+    got = oracle.evolve3(psi, V, 0.21, 11, **ANISO3)
+    want = oracle.evolve(psi2, V2, 0.21, 11, **{k: v for k, v in ANISO3.items() if k != "dz"})
+    for z in range(nz):
+        assert rel(got[z], want) < 1e-13
+
+
+@pytest.mark.parametrize("bc", ["periodic", "closed"])
+def test_3d_energy_equals_dense_expectation(bc):
+    n3 = (4, 6, 4) if bc == "periodic" else (3, 5, 4)
+    psi, V = _rand3(n3, 86)
+    n, e = oracle.observables3(psi, V, bc=bc, **ANISO3)
+    H = dense.full_h3(n3, V, bc=bc, **ANISO3)
+    v = psi.reshape(-1)
+    assert abs(n - np.vdot(v, v).real) < 1e-13
+    assert abs(e - (np.vdot(v, H @ v).real / np.vdot(v, v).real)) < 1e-12
+
+
+def test_3d_forward_then_backward_and_norm():
+    psi, V = _rand3((10, 8, 6), 87)
+    fwd = oracle.evolve3(psi, V, 0.3, 25, **ANISO3)
+    assert abs(np.sum(np.abs(fwd) ** 2) - 1.0) < 1e-13
+    assert rel(oracle.evolve3(fwd, V, -0.3, 25, **ANISO3), psi) < 1e-13
+
+
+def test_3d_rejects_bad_arguments():
+    psi, V = _rand3((4, 4, 3), 1)
+    with pytest.raises(ValueError):
+        oracle.evolve3(psi, V, 0.1, 1)          # odd side under periodic boundaries
+    with pytest.raises(ValueError):
+        oracle.evolve3(psi, V[:, :, :2], 0.1, 1, bc="closed")
