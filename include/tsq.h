@@ -12,7 +12,9 @@
  * second-order product, Eq. "secondorder").
  *
  * Conventions
- *   - Mesh: nx * ny sites, row-major (y, x), x fastest.  psi is interleaved
+ *   - Mesh: nx * ny sites, row-major (y, x), x fastest; a 3D mesh (nz > 1) is
+ *     (z, y, x), x fastest, and its step adds the z factors symmetrically:
+ *       Ox Oy Oz Ex Ey Ez P Ez Ey Ex Oz Oy Ox, eps0 summing all three axes.  psi is interleaved
  *     complex: complex128 = two doubles (re, im) per site, complex64 = two
  *     floats.  V is one double per site.
  *   - One step is U2(dt) = exp(-i dt H / hbar) + O(dt^3) applied as
@@ -58,7 +60,7 @@
 extern "C" {
 #endif
 
-#define TSQ_ABI_VERSION 3
+#define TSQ_ABI_VERSION 4
 
 typedef enum {
     TSQ_OK = 0,
@@ -86,6 +88,9 @@ typedef struct {
     int32_t order;    /* 2: U2(dt) per step (Eq. "secondorder"); 4: U4(dt) per step,
                          U2(p dt)^2 U2((1-4p) dt) U2(p dt)^2, p = 1/(4 - 4^(1/3))
                          (Eq. "fourthorder"); 0 means 2 */
+    int32_t nz;       /* 0 or 1: a 2D mesh.  >= 2: a 3D mesh (nz, ny, nx), the extension
+                         to three dimensions of Sec. 5 (periodic, even sides, order 2) */
+    double dz;        /* mesh spacing along z (3D meshes); finite, > 0 */
 } tsq_problem;
 
 typedef struct tsq_plan tsq_plan; /* opaque, host memory */
@@ -101,7 +106,8 @@ const char* tsq_last_error(void);
  * (sin al and 1 - cos al = 2 sin^2(al/2) for tau = dt/2 and dt along each
  * axis) and a default schedule.  Host only; touches no device.
  * Errors: TSQ_ERR_ARG (null, bad constant, order not 0/2/4), TSQ_ERR_SHAPE,
- * TSQ_ERR_DTYPE.  *out is set only on TSQ_OK. */
+ * TSQ_ERR_DTYPE, TSQ_ERR_UNSUPPORTED (a 3D mesh with closed boundaries or
+ * order 4).  *out is set only on TSQ_OK. */
 int tsq_plan_create(const tsq_problem* problem, tsq_plan** out);
 
 /* Free a plan (NULL is accepted). */
@@ -113,7 +119,9 @@ int tsq_plan_destroy(tsq_plan* plan);
  * p dt and (1-4p) dt) and reduction scratch.  Host only. */
 int tsq_workspace_size(const tsq_plan* plan, size_t* bytes);
 
-/* Schedule of the fused step kernel.  Every schedule applies the same
+/* Schedule of the fused step kernel (2D meshes; a 3D mesh runs one step per
+ * pass with its own tiling and takes only segment_rows, as the planes one
+ * block marches).  Every schedule applies the same
  * operations in the same order to every site, so results are bitwise
  * identical across schedules; only speed changes. */
 typedef struct {
@@ -164,7 +172,7 @@ int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws
  * (Sec. 2, footnote to Eq. "evolution", citing Poulin et al.): here step n,
  * from t_n to t_n + dt, is U2(dt) with the potential frozen at the step's
  * midpoint, V0 + f_n W with f_n = f(t_n + dt/2), which keeps the product second
- * order for smooth f.  Periodic order-2 plans only; every step's phase factor
+ * order for smooth f.  Periodic order-2 plans of 2D meshes only; every step's phase factor
  * exp(-i dt (V0 + f_n W + eps0) / hbar) is formed in FP64 inside the march, so
  * up to 4 steps fuse per pass (a plan scheduled deeper runs 4). */
 
@@ -172,7 +180,7 @@ int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws
  * each) in `ws`: per site dt (V0 + eps0) / hbar and dt W / hbar (16 bytes, the
  * place of the phase table).  Records `ws` for tsq_evolve_td; a later
  * tsq_set_potential makes the workspace time-independent again.
- * Errors: TSQ_ERR_ARG (null), TSQ_ERR_UNSUPPORTED (order 4 or closed mesh),
+ * Errors: TSQ_ERR_ARG (null), TSQ_ERR_UNSUPPORTED (order 4, closed or 3D mesh),
  * TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
 int tsq_set_potential_td(tsq_plan* plan, const double* V0_dev, const double* W_dev, void* ws,
                          size_t ws_bytes, void* stream);
@@ -212,7 +220,7 @@ typedef struct tsq_batch tsq_batch; /* opaque, host memory */
  * psi_dev[i] with workspace ws[i] (tsq_set_potential must already have been
  * called with that workspace) for steps[i] >= 0 steps.  All plans must have
  * the same dtype and be periodic and of order 2, with a time-independent
- * potential (else TSQ_ERR_UNSUPPORTED).
+ * potential on a 2D mesh (else TSQ_ERR_UNSUPPORTED).
  * `schedule` (NULL = defaults; segment_rows is ignored, the
  * batch sizes its own tiles) applies to every problem.  The batch records the
  * device pointers, which must stay valid while it is used; plans may be

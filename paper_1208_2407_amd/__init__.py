@@ -57,7 +57,7 @@ class tsq_problem(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("mass", ctypes.c_double), ("hbar", ctypes.c_double),
                 ("dt", ctypes.c_double), ("bc", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("order", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("nz", ctypes.c_int32), ("dz", ctypes.c_double)]
 
 
 _lib = None
@@ -240,9 +240,12 @@ class Plan:
     """
 
     def __init__(self, nx: int, ny: int, dt: float, dtype: str = "c128", *, dx=1.0, dy=1.0,
-                 mass=1.0, hbar=1.0, bc="periodic", order: int = 2, device="cuda"):
+                 mass=1.0, hbar=1.0, bc="periodic", order: int = 2, nz: int = 0, dz=1.0,
+                 device="cuda"):
+        """nz >= 2 makes a 3D mesh: psi and V are then (nz, ny, nx) tensors."""
         self.problem = tsq_problem(int(nx), int(ny), float(dx), float(dy), float(mass),
-                                   float(hbar), float(dt), BCS[bc], DTYPES[dtype], int(order))
+                                   float(hbar), float(dt), BCS[bc], DTYPES[dtype], int(order),
+                                   int(nz), float(dz))
         self.dtype = dtype
         self.handle = tsq_plan_create(self.problem)
         self.device = device
@@ -257,6 +260,12 @@ class Plan:
             except Exception:
                 pass
             self.handle = None
+
+    @property
+    def shape(self) -> Tuple[int, ...]:
+        """(ny, nx) of a 2D mesh, (nz, ny, nx) of a 3D one."""
+        p = self.problem
+        return (p.nz, p.ny, p.nx) if p.nz >= 2 else (p.ny, p.nx)
 
     @property
     def workspace_bytes(self) -> int:
@@ -284,8 +293,8 @@ class Plan:
 
     def set_potential(self, V) -> None:
         torch = _torch()
-        if V.dtype != torch.float64 or not V.is_contiguous() or tuple(V.shape) != (self.problem.ny, self.problem.nx):
-            raise ValueError("V must be a contiguous float64 (ny, nx) device tensor")
+        if V.dtype != torch.float64 or not V.is_contiguous() or tuple(V.shape) != self.shape:
+            raise ValueError(f"V must be a contiguous float64 {self.shape} device tensor")
         ws = self.workspace()
         tsq_set_potential(self.handle, V.data_ptr(), ws.data_ptr(), ws.numel(),
                           _stream_handle(V.device))
@@ -295,8 +304,8 @@ class Plan:
         """Time-dependent potential V0 + f(t) W (modulations given to evolve_td)."""
         torch = _torch()
         for name, a in (("V0", V0), ("W", W)):
-            if a.dtype != torch.float64 or not a.is_contiguous() or tuple(a.shape) != (self.problem.ny, self.problem.nx):
-                raise ValueError(f"{name} must be a contiguous float64 (ny, nx) device tensor")
+            if a.dtype != torch.float64 or not a.is_contiguous() or tuple(a.shape) != self.shape:
+                raise ValueError(f"{name} must be a contiguous float64 {self.shape} device tensor")
         ws = self.workspace()
         tsq_set_potential_td(self.handle, V0.data_ptr(), W.data_ptr(), ws.data_ptr(), ws.numel(),
                              _stream_handle(V0.device))
@@ -314,8 +323,8 @@ class Plan:
     def _check_psi(self, psi) -> None:
         torch = _torch()
         want = torch.complex128 if self.dtype == "c128" else torch.complex64
-        if psi.dtype != want or not psi.is_contiguous() or tuple(psi.shape) != (self.problem.ny, self.problem.nx):
-            raise ValueError(f"psi must be a contiguous {want} (ny, nx) device tensor")
+        if psi.dtype != want or not psi.is_contiguous() or tuple(psi.shape) != self.shape:
+            raise ValueError(f"psi must be a contiguous {want} {self.shape} device tensor")
 
     def evolve(self, psi, steps: int):
         """Apply U2(dt)^steps to psi in place and return it."""
@@ -399,14 +408,14 @@ def _dtype_name(t) -> str:
     raise ValueError(f"psi dtype {t.dtype} is not complex64/complex128")
 
 
-def evolve(psi, V, dt: float, steps: int, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
+def evolve(psi, V, dt: float, steps: int, *, dx=1.0, dy=1.0, dz=1.0, mass=1.0, hbar=1.0,
            bc="periodic", order: int = 2, steps_per_pass: int = 0, segment_rows: int = 0,
            pairs_per_lane: int = 0, phase_store: int = 0):
-    """Evolve the device tensor psi (ny, nx) in place by `steps` steps of U2 (order 2)
-    or U4 (order 4)."""
-    ny, nx = psi.shape
+    """Evolve the device tensor psi (ny, nx), or (nz, ny, nx) for a 3D mesh, in place by
+    `steps` steps of U2 (order 2) or U4 (order 4)."""
+    nz, ny, nx = psi.shape if psi.dim() == 3 else (0,) + tuple(psi.shape)
     plan = Plan(nx, ny, dt, _dtype_name(psi), dx=dx, dy=dy, mass=mass, hbar=hbar, bc=bc,
-                order=order, device=psi.device)
+                order=order, nz=nz, dz=dz, device=psi.device)
     plan.set_schedule(steps_per_pass, segment_rows, pairs_per_lane, phase_store)
     plan.set_potential(V)
     plan.evolve(psi, steps)
@@ -426,8 +435,9 @@ def evolve_td(psi, V0, W, f, dt: float, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0,
     return psi
 
 
-def observables(psi, V, *, dx=1.0, dy=1.0, mass=1.0, hbar=1.0, bc="periodic") -> Tuple[float, float]:
-    ny, nx = psi.shape
+def observables(psi, V, *, dx=1.0, dy=1.0, dz=1.0, mass=1.0, hbar=1.0,
+                bc="periodic") -> Tuple[float, float]:
+    nz, ny, nx = psi.shape if psi.dim() == 3 else (0,) + tuple(psi.shape)
     plan = Plan(nx, ny, 0.0, _dtype_name(psi), dx=dx, dy=dy, mass=mass, hbar=hbar, bc=bc,
-                device=psi.device)
+                nz=nz, dz=dz, device=psi.device)
     return plan.observables(psi, V)

@@ -37,23 +37,30 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libtsq)")
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+def build(verbose: bool = False, jobs: int = 0, incremental: bool = False) -> str:
     """Compile every csrc/*.hip (device) and csrc/*.cpp (host) file in parallel and
-    link libtsq.so."""
+    link libtsq.so.  incremental: skip a source whose object is newer than it and
+    than every header (csrc/*.h, *.hpp, include/*.h)."""
     os.makedirs(OUT_DIR, exist_ok=True)
     cc = hipcc()
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
+    headers = (glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(CSRC, "*.hpp"))
+               + glob.glob(os.path.join(ROOT, "include", "*.h")))
+    newest_header = max((os.path.getmtime(h) for h in headers), default=0.0)
     cmds = []
     objs = []
     for src in srcs:
         obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
+        objs.append(obj)
+        if (incremental and os.path.exists(obj)
+                and os.path.getmtime(obj) > max(os.path.getmtime(src), newest_header)):
+            continue
         dev = src.endswith(".hip")
         cmds.append([cc, "-c", src, "-o", obj] + COMMON + (DEVICE if dev else []))
-        objs.append(obj)
     if verbose:
         for c in cmds:
             print(" ".join(c), flush=True)
-    jobs = jobs or min(len(cmds), os.cpu_count() or 1, 8)
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 1, 8))
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         for r in ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds):
             if r.returncode != 0:
@@ -69,4 +76,4 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

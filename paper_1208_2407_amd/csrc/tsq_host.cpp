@@ -30,7 +30,9 @@ struct SubStep {
 
 struct tsq_plan {
     tsq_problem p;
-    double Jx, Jy, eps0;
+    double Jx, Jy, Jz, eps0;
+    bool three_d;                    // nz >= 2
+    tsq::Coef64 ozh, oz2;            // z factors of a 3D mesh, tau = dt/2 and dt
     tsq::Coef64 oxh, oyh, ox2, oy2;   // of kind 0
     int nkinds;
     SubStep kind[2];
@@ -365,9 +367,9 @@ int tsq_batch_create(tsq_plan* const* plans, void* const* psi, void* const* ws, 
         if (!plans[i] || !psi[i] || !ws[i]) return fail(TSQ_ERR_ARG, "null entry %d", i);
         if (steps[i] < 0) return fail(TSQ_ERR_ARG, "steps[%d] = %lld < 0", i, (long long)steps[i]);
         if (plans[i]->p.dtype != dtype) return fail(TSQ_ERR_DTYPE, "batch mixes dtypes (entry %d)", i);
-        if (plans[i]->p.order != 2 || plans[i]->p.bc != TSQ_BC_PERIODIC)
+        if (plans[i]->p.order != 2 || plans[i]->p.bc != TSQ_BC_PERIODIC || plans[i]->three_d)
             return fail(TSQ_ERR_UNSUPPORTED,
-                        "entry %d: the batched form runs periodic order-2 plans only", i);
+                        "entry %d: the batched form runs periodic order-2 2D plans only", i);
         if (plans[i]->ws_bound != ws[i])
             return fail(TSQ_ERR_STATE, "entry %d: workspace is not the one given to tsq_set_potential", i);
         if (plans[i]->td)
@@ -541,6 +543,19 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
         return fail(TSQ_ERR_DTYPE, "unknown dtype %d", pr->dtype);
     if (pr->order != 0 && pr->order != 2 && pr->order != 4)
         return fail(TSQ_ERR_ARG, "order must be 2 or 4 (got %d)", pr->order);
+    const bool three_d = pr->nz >= 2;
+    if (pr->nz < 0) return fail(TSQ_ERR_SHAPE, "nz must be >= 0 (got %d)", pr->nz);
+    if (three_d) {
+        if (!finite_pos(pr->dz)) return fail(TSQ_ERR_ARG, "dz must be finite and > 0 (%g)", pr->dz);
+        if (pr->bc != TSQ_BC_PERIODIC)
+            return fail(TSQ_ERR_UNSUPPORTED, "3D meshes run with periodic boundaries only");
+        if (pr->order == 4) return fail(TSQ_ERR_UNSUPPORTED, "3D meshes run the order-2 step only");
+        if (pr->nz & 1)
+            return fail(TSQ_ERR_SHAPE, "nz = %d: periodic boundaries need even sides", pr->nz);
+        if ((long long)pr->nx * (long long)pr->ny * (long long)pr->nz > 0x7fffffffLL)
+            return fail(TSQ_ERR_SHAPE, "mesh %d x %d x %d exceeds 2^31-1 sites", pr->nx, pr->ny,
+                        pr->nz);
+    }
 
     tsq_plan* p = new (std::nothrow) tsq_plan();
     if (!p) return fail(TSQ_ERR_ARG, "out of host memory");
@@ -549,6 +564,16 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
     p->Jx = hb * hb / (2.0 * m * pr->dx * pr->dx);
     p->Jy = hb * hb / (2.0 * m * pr->dy * pr->dy);
     p->eps0 = hb * hb / (m * pr->dx * pr->dx) + hb * hb / (m * pr->dy * pr->dy);
+    p->three_d = three_d;
+    p->Jz = 0.0;
+    if (three_d) {
+        p->Jz = hb * hb / (2.0 * m * pr->dz * pr->dz);
+        p->eps0 += hb * hb / (m * pr->dz * pr->dz);
+        p->ozh = block_coef(0.5 * pr->dt, p->Jz, hb);
+        p->oz2 = block_coef(pr->dt, p->Jz, hb);
+    } else {
+        p->p.nz = 1;
+    }
     if (p->p.order == 0) p->p.order = 2;
     double dts[2] = {pr->dt, 0.0};
     p->nkinds = 1;
@@ -571,7 +596,7 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
     p->ox2 = p->kind[0].ox2;
     p->oy2 = p->kind[0].oy2;
     resolve_schedule(tsq_schedule{0, 0, 0, 0}, p->sched);
-    p->sites = (size_t)pr->nx * (size_t)pr->ny;
+    p->sites = (size_t)pr->nx * (size_t)pr->ny * (size_t)p->p.nz;
     p->elem = pr->dtype == TSQ_C128 ? 16 : 8;
     p->pelem = 16;  // complex128: exp(-i phi); complex64: hi + lo complex floats
     p->off_psi2 = 0;
@@ -635,6 +660,11 @@ int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int3
     if (plan->p.order == 4 && steps > 10000000LL)
         return fail(TSQ_ERR_ARG, "order-4 evolution of %lld steps is too long for one call",
                     (long long)steps);
+    if (plan->three_d) {  // one step per pass
+        *passes = steps;
+        *copy_back = (steps & 1) ? 1 : 0;
+        return ok();
+    }
     std::vector<PassGroup> groups;
     const int S = plan->td ? std::min(plan->sched.steps_per_pass, tsq::kMaxTdSteps)
                            : plan->sched.steps_per_pass;
@@ -669,8 +699,9 @@ int tsq_set_potential_td(tsq_plan* plan, const double* V0, const double* W, void
     if (!plan || !V0 || !W) return fail(TSQ_ERR_ARG, "null plan or potential");
     if (plan->p.order != 2)
         return fail(TSQ_ERR_UNSUPPORTED, "time-dependent potentials run with order-2 plans only");
-    if (plan->p.bc != TSQ_BC_PERIODIC)
-        return fail(TSQ_ERR_UNSUPPORTED, "time-dependent potentials run on periodic meshes only");
+    if (plan->p.bc != TSQ_BC_PERIODIC || plan->three_d)
+        return fail(TSQ_ERR_UNSUPPORTED,
+                    "time-dependent potentials run on periodic 2D meshes only");
     int rc = check_ws(plan, ws, ws_bytes);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
@@ -756,6 +787,58 @@ int run_evolution(tsq_plan* plan, void* psi, int64_t steps, void* ws, hipStream_
     return ok();
 }
 
+// Three-dimensional mesh: one step per pass.
+int run_evolution3(tsq_plan* plan, void* psi, int64_t steps, void* ws, hipStream_t s) {
+    char* w = static_cast<char*>(ws);
+    void* buf[2] = {psi, w + plan->off_psi2};
+    int cus = device_cus();
+    if (cus <= 0) cus = 256;
+    tsq::Pass3Desc d;
+    d.ptab = w + plan->kind[0].off_ptab;
+    d.nx = plan->p.nx;
+    d.ny = plan->p.ny;
+    d.nz = plan->p.nz;
+    d.oh[0] = plan->oxh;
+    d.oh[1] = plan->oyh;
+    d.oh[2] = plan->ozh;
+    d.o2[0] = plan->ox2;
+    d.o2[1] = plan->oy2;
+    d.o2[2] = plan->oz2;
+    // segment height: one round of resident blocks (tiles = strips x slabs x
+    // segments), at least 2K plane pairs; a schedule's segment_rows sets it
+    // (segment_rows / 2 plane pairs)
+    int seg[2];
+    for (int last = 0; last < 2; ++last) {
+        const int K = last ? 2 : 1;
+        const long long strips = (d.nx + (tsq::kWaveSize - 2 * K) * 2 - 1) / ((tsq::kWaveSize - 2 * K) * 2);
+        const long long slabs = (d.ny / 2 + tsq::kWaves3 - 2 * K - 1) / (tsq::kWaves3 - 2 * K);
+        int bpc = tsq::march3_blocks_per_cu(plan->p.dtype, last != 0);
+        if (bpc <= 0) bpc = 1;
+        const long long pairs = d.nz / 2;
+        long long segs = (long long)cus * bpc / (strips * slabs);
+        if (segs < 1) segs = 1;
+        if (segs > pairs) segs = pairs;
+        long long per = (pairs + segs - 1) / segs;
+        if (per < 2LL * K) per = 2LL * K;
+        if (plan->sched.segment_rows > 0) per = plan->sched.segment_rows / 2;
+        seg[last] = (int)std::min<long long>(per, pairs);
+    }
+    for (int64_t i = 0; i < steps; ++i) {
+        d.src = buf[i & 1];
+        d.dst = buf[(i + 1) & 1];
+        d.first = i == 0;
+        d.last = i + 1 == steps;
+        d.seg_pairs = seg[d.last ? 1 : 0];
+        hipError_t e = tsq::launch_pass3(plan->p.dtype, d, s);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "3D pass launch: %s", hipGetErrorString(e));
+    }
+    if (steps & 1) {
+        hipError_t e = hipMemcpyAsync(psi, buf[1], plan->sites * plan->elem, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "copy back: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -766,6 +849,7 @@ int tsq_evolve(tsq_plan* plan, void* psi, int64_t steps, void* ws, size_t ws_byt
     if (plan->td)
         return fail(TSQ_ERR_STATE, "the workspace holds a time-dependent potential: use tsq_evolve_td");
     if (steps == 0) return ok();
+    if (plan->three_d) return run_evolution3(plan, psi, steps, ws, static_cast<hipStream_t>(stream));
     return run_evolution(plan, psi, steps, ws, static_cast<hipStream_t>(stream), nullptr);
 }
 
@@ -792,10 +876,16 @@ int tsq_observables(const tsq_plan* plan, const void* psi, const double* V, doub
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* scratch = reinterpret_cast<double*>(static_cast<char*>(ws) + plan->off_scratch);
     double* result = scratch + 2 * tsq::kReduceBlocks;
-    const int nblocks = plan->p.ny < tsq::kReduceBlocks ? plan->p.ny : tsq::kReduceBlocks;
-    hipError_t e = tsq::launch_observables(plan->p.dtype, psi, V, plan->p.nx, plan->p.ny, plan->Jx,
-                                           plan->Jy, plan->eps0, plan->p.bc == TSQ_BC_CLOSED,
-                                           scratch, nblocks, result, s);
+    const long long rows = (long long)plan->p.ny * plan->p.nz;
+    const int nblocks = rows < tsq::kReduceBlocks ? (int)rows : tsq::kReduceBlocks;
+    hipError_t e = plan->three_d
+                       ? tsq::launch_observables3(plan->p.dtype, psi, V, plan->p.nx, plan->p.ny,
+                                                  plan->p.nz, plan->Jx, plan->Jy, plan->Jz,
+                                                  plan->eps0, scratch, nblocks, result, s)
+                       : tsq::launch_observables(plan->p.dtype, psi, V, plan->p.nx, plan->p.ny,
+                                                 plan->Jx, plan->Jy, plan->eps0,
+                                                 plan->p.bc == TSQ_BC_CLOSED, scratch, nblocks,
+                                                 result, s);
     if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "observables launch: %s", hipGetErrorString(e));
     double host[2];
     e = hipMemcpyAsync(host, result, sizeof host, hipMemcpyDeviceToHost, s);

@@ -257,6 +257,57 @@ def drive(dt: float, steps: int, amplitude: float = 0.2, omega: float = 0.5,
     return amplitude * np.sin(omega * t + phase)
 
 
+# Three-dimensional meshes (nz, ny, nx): one Gaussian packet in a harmonic
+# well, both separable, so the fields are outer products of 1D vectors.
+
+@dataclasses.dataclass
+class Problem3:
+    nx: int
+    ny: int
+    nz: int
+    dt: float
+    steps: int
+    sigma: float
+    k: Tuple[float, float, float]
+    omega: float
+    mass: float = 1.0
+    hbar: float = 1.0
+
+    @property
+    def sites(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def site_steps(self) -> int:
+        return self.sites * self.steps
+
+
+def packet_in_well3(n: int, seed: int, dt: float = 0.05, steps: int = 200, sigma: float = 8.0,
+                    omega: float = 0.02, nz: int = 0, ny: int = 0) -> Problem3:
+    """One packet at the centre of an n x ny x nz mesh, momentum drawn U[-0.5, 0.5]^3."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = tuple(float(v) for v in rng.uniform(-0.5, 0.5, 3))
+    return Problem3(n, ny or n, nz or n, dt, steps, sigma, k, omega)
+
+
+def state3(p: Problem3, device="cpu", dtype=torch.complex128) -> torch.Tensor:
+    """Unit-norm packet exp(-r^2/(4 sigma^2) + i k.r) as (nz, ny, nx)."""
+    vecs = []
+    for n, kk in ((p.nx, p.k[0]), (p.ny, p.k[1]), (p.nz, p.k[2])):
+        x = np.arange(n) - n / 2
+        v = np.exp(-x * x / (4 * p.sigma ** 2) + 1j * kk * x)
+        vecs.append(torch.from_numpy(v / np.linalg.norm(v)).to(device))
+    fx, fy, fz = vecs
+    return (fz[:, None, None] * fy[None, :, None] * fx[None, None, :]).to(dtype).contiguous()
+
+
+def potential3(p: Problem3, device="cpu") -> torch.Tensor:
+    """V = m omega^2 r^2 / 2 as (nz, ny, nx) float64."""
+    k = 0.5 * p.mass * p.omega ** 2
+    v = [torch.from_numpy(k * (np.arange(n) - n / 2) ** 2).to(device) for n in (p.nx, p.ny, p.nz)]
+    return (v[2][:, None, None] + v[1][None, :, None] + v[0][None, None, :]).contiguous()
+
+
 def random_state(nx: int, ny: int, seed: int) -> np.ndarray:
     """Unit-norm complex Gaussian noise: a state with every wavenumber present."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -33,11 +33,12 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version():
-    assert tsq.tsq_abi_version() == 3
+    assert tsq.tsq_abi_version() == 4
 
 
 def problem(**kw):
-    base = dict(nx=64, ny=32, dx=1.0, dy=1.0, mass=1.0, hbar=1.0, dt=0.1, bc=0, dtype=1, order=2)
+    base = dict(nx=64, ny=32, dx=1.0, dy=1.0, mass=1.0, hbar=1.0, dt=0.1, bc=0, dtype=1, order=2,
+                nz=0, dz=1.0)
     base.update(kw)
     return tsq.tsq_problem(*[base[k] for k, _ in tsq.tsq_problem._fields_])
 
@@ -49,6 +50,9 @@ def problem(**kw):
     (dict(dt=math.nan), -1), (dict(dt=math.inf), -1),
     (dict(dtype=7), -3), (dict(bc=5), -1), (dict(order=3), -1),
     (dict(order=1), -1),
+    (dict(nz=3), -2), (dict(nz=-1), -2), (dict(nz=4, dz=0.0), -1),
+    (dict(nz=4, bc=1), -7), (dict(nz=4, order=4), -7),
+    (dict(nx=2048, ny=2048, nz=1024), -2),
 ])
 def test_plan_create_rejects(kw, status):
     with pytest.raises(tsq.TsqError) as ei:
@@ -172,5 +176,18 @@ def test_closed_meshes_accept_odd_sides_and_one_pair_per_lane():
         with pytest.raises(tsq.TsqError) as ei:
             tsq.tsq_plan_set_schedule(h, sched(3, 0, 2, 1))
         assert ei.value.status == -1
+    finally:
+        tsq.tsq_plan_destroy(h)
+
+
+def test_3d_plan_workspace_and_passes():
+    h = tsq.tsq_plan_create(problem(nx=64, ny=32, nz=16, dz=0.7))
+    try:
+        sites = 64 * 32 * 16
+        assert tsq.tsq_workspace_size(h) >= sites * (16 + 16)
+        assert tsq.tsq_evolve_passes(h, 7) == (7, True)   # one step per pass
+        assert tsq.tsq_evolve_passes(h, 8) == (8, False)
+        lib = tsq.load_library()
+        assert lib.tsq_set_potential_td(h, 16, 16, 256, 1 << 30, None) == -7
     finally:
         tsq.tsq_plan_destroy(h)
