@@ -3,6 +3,6 @@
 
 namespace tsq {
 
-const void* march3_ptr_c128(bool last) { return pick_kernel3<C128>(last); }
+const void* march3_ptr_c128(bool close) { return pick_kernel3<C128>(close); }
 
 }  // namespace tsq

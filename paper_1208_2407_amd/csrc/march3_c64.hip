@@ -3,6 +3,6 @@
 
 namespace tsq {
 
-const void* march3_ptr_c64(bool last) { return pick_kernel3<C64>(last); }
+const void* march3_ptr_c64(bool close) { return pick_kernel3<C64>(close); }
 
 }  // namespace tsq

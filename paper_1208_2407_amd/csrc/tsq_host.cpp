@@ -660,9 +660,9 @@ int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int3
     if (plan->p.order == 4 && steps > 10000000LL)
         return fail(TSQ_ERR_ARG, "order-4 evolution of %lld steps is too long for one call",
                     (long long)steps);
-    if (plan->three_d) {  // one step per pass
-        *passes = steps;
-        *copy_back = (steps & 1) ? 1 : 0;
+    if (plan->three_d) {  // one step per pass, then a closing pass
+        *passes = steps > 0 ? steps + 1 : 0;
+        *copy_back = (steps > 0 && !(steps & 1)) ? 1 : 0;
         return ok();
     }
     std::vector<PassGroup> groups;
@@ -805,34 +805,28 @@ int run_evolution3(tsq_plan* plan, void* psi, int64_t steps, void* ws, hipStream
     d.o2[1] = plan->oy2;
     d.o2[2] = plan->oz2;
     // segment height: one round of resident blocks (tiles = strips x slabs x
-    // segments), at least 2K plane pairs; a schedule's segment_rows sets it
+    // segments), at least 2 plane pairs; a schedule's segment_rows sets it
     // (segment_rows / 2 plane pairs)
-    int seg[2];
-    for (int last = 0; last < 2; ++last) {
-        const int K = last ? 2 : 1;
-        const long long strips = (d.nx + (tsq::kWaveSize - 2 * K) * 2 - 1) / ((tsq::kWaveSize - 2 * K) * 2);
-        const long long slabs = (d.ny / 2 + tsq::kWaves3 - 2 * K - 1) / (tsq::kWaves3 - 2 * K);
-        int bpc = tsq::march3_blocks_per_cu(plan->p.dtype, last != 0);
-        if (bpc <= 0) bpc = 1;
-        const long long pairs = d.nz / 2;
-        long long segs = (long long)cus * bpc / (strips * slabs);
-        if (segs < 1) segs = 1;
-        if (segs > pairs) segs = pairs;
-        long long per = (pairs + segs - 1) / segs;
-        if (per < 2LL * K) per = 2LL * K;
-        if (plan->sched.segment_rows > 0) per = plan->sched.segment_rows / 2;
-        seg[last] = (int)std::min<long long>(per, pairs);
-    }
-    for (int64_t i = 0; i < steps; ++i) {
+    const long long strips = (d.nx + (tsq::kWaveSize - 2) * 2 - 1) / ((tsq::kWaveSize - 2) * 2);
+    const long long slabs = (d.ny / 2 + tsq::kWaves3 - 3) / (tsq::kWaves3 - 2);
+    const long long pairs = d.nz / 2;
+    int bpc = tsq::march3_blocks_per_cu(plan->p.dtype, false);
+    if (bpc <= 0) bpc = 1;
+    long long segs = (long long)cus * bpc / (strips * slabs);
+    segs = std::max(1LL, std::min(segs, pairs));
+    long long per = std::max(2LL, (pairs + segs - 1) / segs);
+    if (plan->sched.segment_rows > 0) per = plan->sched.segment_rows / 2;
+    d.seg_pairs = (int)std::min(per, pairs);
+    // steps passes, then the closing odd factors of the last step
+    for (int64_t i = 0; i <= steps; ++i) {
         d.src = buf[i & 1];
         d.dst = buf[(i + 1) & 1];
         d.first = i == 0;
-        d.last = i + 1 == steps;
-        d.seg_pairs = seg[d.last ? 1 : 0];
+        d.close = i == steps;
         hipError_t e = tsq::launch_pass3(plan->p.dtype, d, s);
         if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "3D pass launch: %s", hipGetErrorString(e));
     }
-    if (steps & 1) {
+    if (!(steps & 1)) {  // steps + 1 passes: an odd count ends in the second buffer
         hipError_t e = hipMemcpyAsync(psi, buf[1], plan->sites * plan->elem, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "copy back: %s", hipGetErrorString(e));
     }

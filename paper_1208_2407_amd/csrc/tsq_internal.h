@@ -107,7 +107,8 @@ struct Pass3Desc {
     void* dst;
     const void* ptab;
     int nx, ny, nz;
-    bool first, last;
+    bool first;           // opening odd factors for dt/2 (else dt)
+    bool close;           // a closing pass: only the final odd factors, dt/2
     int seg_pairs;        // plane pairs per tile
     Coef64 oh[3], o2[3];  // tau = dt/2 and tau = dt, per axis
 };
@@ -137,7 +138,7 @@ hipError_t launch_td_table(const double* V0, const double* W, void* table, long 
                            double dt, double eps0, double hbar, hipStream_t s);
 hipError_t launch_pass(int dtype, const PassDesc& d, hipStream_t s);
 hipError_t launch_pass3(int dtype, const Pass3Desc& d, hipStream_t s);
-int march3_blocks_per_cu(int dtype, bool last);
+int march3_blocks_per_cu(int dtype, bool close);
 hipError_t launch_observables3(int dtype, const void* psi, const double* V, int nx, int ny, int nz,
                                double Jx, double Jy, double Jz, double eps0, double* partial,
                                int nblocks, double* result, hipStream_t s);

@@ -20,8 +20,8 @@ const void* march_ptr_c128_closed(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c64_closed(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c128_td(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c64_td(int steps, bool last, int ppl, bool lds);
-const void* march3_ptr_c128(bool last);
-const void* march3_ptr_c64(bool last);
+const void* march3_ptr_c128(bool close);
+const void* march3_ptr_c64(bool close);
 
 namespace {
 
@@ -324,8 +324,8 @@ hipError_t launch_observables3(int dtype, const void* psi, const double* V, int 
     return hipGetLastError();
 }
 
-int march3_blocks_per_cu(int dtype, bool last) {
-    const void* f = dtype == 1 ? march3_ptr_c128(last) : march3_ptr_c64(last);
+int march3_blocks_per_cu(int dtype, bool close) {
+    const void* f = dtype == 1 ? march3_ptr_c128(close) : march3_ptr_c64(close);
     int n = 0;
     if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kWaveSize * kWaves3, 0) != hipSuccess)
         return 0;
@@ -334,7 +334,7 @@ int march3_blocks_per_cu(int dtype, bool last) {
 
 template <class R>
 static hipError_t launch3_with(const void* f, const Pass3Desc& d, hipStream_t s) {
-    const int K = d.last ? 2 : 1;
+    const int K = 1;
     March3Args<R> a;
     a.src = d.src;
     a.dst = d.dst;
@@ -362,7 +362,7 @@ static hipError_t launch3_with(const void* f, const Pass3Desc& d, hipStream_t s)
 }
 
 hipError_t launch_pass3(int dtype, const Pass3Desc& d, hipStream_t s) {
-    const void* f = dtype == 1 ? march3_ptr_c128(d.last) : march3_ptr_c64(d.last);
+    const void* f = dtype == 1 ? march3_ptr_c128(d.close) : march3_ptr_c64(d.close);
     if (!f || d.seg_pairs < 1) return hipErrorInvalidValue;
     hipError_t e = dtype == 1 ? launch3_with<double>(f, d, s) : launch3_with<float>(f, d, s);
     if (e != hipSuccess) return e;

@@ -2,7 +2,8 @@
 // seven-part split that the paper names as its extension to three
 // dimensions (Sec. 5), one time step per pass.  Per step, first factor first:
 //   Ox Oy Oz Ex Ey Ez P Ez Ey Ex Oz Oy Ox   (kinetic factors for dt/2)
-// with consecutive steps sharing their odd factors as in the 2D march.
+// with consecutive steps sharing their odd factors as in the 2D march; a
+// closing pass after the last step applies its final Oz Oy Ox.
 //
 // Tiling: a block of kWaves3 wavefronts owns an x-strip of 64 lanes (two
 // x-sites per lane) times a slab of kWaves3 row pairs (wavefront w holds row
@@ -13,7 +14,7 @@
 // y-pairs join row b of wavefront w with row a of wavefront w+1 through LDS,
 // one block barrier per exchange; z-pairs sit in a lane.  The lanes and
 // wavefronts at the tile edges are halo whose results are discarded (one pair
-// per step per side, like the 2D halo).
+// per side, like the 2D halo).
 #pragma once
 
 #include "tsq_march.hpp"
@@ -106,18 +107,18 @@ __device__ __forceinline__ void odd_y3(Row<R, 2> (&p)[2], Row<R, 2> (&q)[2], R s
     buf ^= 1;
 }
 
-// Stage k of the pipeline (k = 0: the step of the pass; k = 1 on the last
-// pass: the closing odd factors only).  o is the older plane pair, n the newer
-// one; the odd factors act on the boundary planes (o.g, n.f), then, for
-// k = 0, the even factors and the phase on o.
-template <bool LAST, class R, class PT>
-__device__ __forceinline__ void stage3(int k, PlanePair<R>& o, PlanePair<R>& n,
+// The single stage of a pass.  o is the older plane pair, n the newer one; the
+// odd factors act on the boundary planes (o.g, n.f), then the even factors
+// and the phase on o.  A closing pass (CLOSE, after the last step) applies
+// only the closing odd factors, for dt/2.
+template <bool CLOSE, class R, class PT>
+__device__ __forceinline__ void stage3(PlanePair<R>& o, PlanePair<R>& n,
                                        const March3Args<R>& a, const XPairs<1, false>& xm,
                                        const PlanePhase<PT>& ph, Exchange3<R>& x, int& buf,
                                        int w, int lane) {
-    const R oxs = k == 0 ? a.o1s[0] : a.ehs[0], oxd = k == 0 ? a.o1d[0] : a.ehd[0];
-    const R oys = k == 0 ? a.o1s[1] : a.ehs[1], oyd = k == 0 ? a.o1d[1] : a.ehd[1];
-    const R ozs = k == 0 ? a.o1s[2] : a.ehs[2], ozd = k == 0 ? a.o1d[2] : a.ehd[2];
+    const R oxs = CLOSE ? a.ehs[0] : a.o1s[0], oxd = CLOSE ? a.ehd[0] : a.o1d[0];
+    const R oys = CLOSE ? a.ehs[1] : a.o1s[1], oyd = CLOSE ? a.ehd[1] : a.o1d[1];
+    const R ozs = CLOSE ? a.ehs[2] : a.o1s[2], ozd = CLOSE ? a.ehd[2] : a.o1d[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         odd_x<false>(o.g[r], oxs, oxd, xm);
@@ -126,7 +127,7 @@ __device__ __forceinline__ void stage3(int k, PlanePair<R>& o, PlanePair<R>& n,
     odd_y3(o.g, n.f, oys, oyd, x, buf, w, lane);
 #pragma unroll
     for (int r = 0; r < 2; ++r) pair_y(o.g[r], n.f[r], ozs, ozd);
-    if (k == 0) {
+    if constexpr (!CLOSE) {
         const R es[3] = {a.ehs[0], a.ehs[1], a.ehs[2]};
         const R ed[3] = {a.ehd[0], a.ehd[1], a.ehd[2]};
 #pragma unroll
@@ -158,17 +159,17 @@ __device__ __forceinline__ void stage3(int k, PlanePair<R>& o, PlanePair<R>& n,
 // One run of plane pairs [q0, q1) of one column (strip, slab) of one pass;
 // wavefront w of the block.
 // Register homes as in the 2D march: the plane pair entering in iteration j
-// stays in home j mod NH until stored K iterations later.  The phase of the
+// stays in home j mod 3 until stored one iteration later.  The phase of the
 // pair stage 0 completes is loaded one iteration ahead into one register
 // home, right after the stage has used the previous one: the phase of pair j
 // is loaded in iteration j and used in iteration j+1.
-template <class T, bool LAST>
+template <class T, bool CLOSE>
 __device__ __forceinline__ void march3_tile(const March3Args<typename T::R>& a, int strip,
                                             int slab, int q0, int q1, bool rev, int w, int lane,
                                             Exchange3<typename T::R>& x, int& buf) {
     using R = typename T::R;
     using PT = typename T::PT;
-    constexpr int K = LAST ? 2 : 1;
+    constexpr int K = 1;           // one stage: one step, or the closing odd factors
     constexpr int HL = K;          // halo lanes (x) and halo wavefronts (y) per side
     constexpr int NH = K + 2;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -256,12 +257,8 @@ __device__ __forceinline__ void march3_tile(const March3Args<typename T::R>& a, 
     auto iteration = [&](auto U) {
         constexpr int u = decltype(U)::value;
         load_psi(home[(u + 1) % NH]);  // the last iteration loads one pair more than it uses
-        static_for<K>([&](auto KK) {
-            constexpr int k = decltype(KK)::value;
-            stage3<LAST>(k, home[(u - 1 - k + 2 * NH) % NH], home[(u - k + 2 * NH) % NH], a, xm,
-                         ph, x, buf, w, lane);
-            if constexpr (k == 0) load_phase(ph);  // the phase of the pair stage 0 completes next
-        });
+        stage3<CLOSE>(home[(u - 1 + NH) % NH], home[u % NH], a, xm, ph, x, buf, w, lane);
+        if constexpr (!CLOSE) load_phase(ph);  // the phase of the pair completed next
         store_out(home[(u - K + 2 * NH) % NH]);
         q += rev ? -1 : 1;
         return q != qend;
@@ -272,7 +269,7 @@ __device__ __forceinline__ void march3_tile(const March3Args<typename T::R>& a, 
     }
 }
 
-template <class T, bool LAST>
+template <class T, bool CLOSE>
 __global__ void __launch_bounds__(kWaveSize * kWaves3)
 march3_kernel(const March3Args<typename T::R> a) {
     __shared__ Exchange3<typename T::R> xch;
@@ -294,13 +291,13 @@ march3_kernel(const March3Args<typename T::R> a) {
     const int q0 = seg * a.seg_pairs;
     const int q1 = min(q0 + a.seg_pairs, a.nz >> 1);
     int buf = 0;
-    march3_tile<T, LAST>(a, strip, slab, q0, q1, seg & 1, w, lane, xch, buf);
+    march3_tile<T, CLOSE>(a, strip, slab, q0, q1, seg & 1, w, lane, xch, buf);
 }
 
 template <class T>
-const void* pick_kernel3(bool last) {
-    return last ? reinterpret_cast<const void*>(&march3_kernel<T, true>)
-                : reinterpret_cast<const void*>(&march3_kernel<T, false>);
+const void* pick_kernel3(bool close) {
+    return close ? reinterpret_cast<const void*>(&march3_kernel<T, true>)
+                 : reinterpret_cast<const void*>(&march3_kernel<T, false>);
 }
 
 }  // namespace

@@ -185,8 +185,9 @@ def test_3d_plan_workspace_and_passes():
     try:
         sites = 64 * 32 * 16
         assert tsq.tsq_workspace_size(h) >= sites * (16 + 16)
-        assert tsq.tsq_evolve_passes(h, 7) == (7, True)   # one step per pass
-        assert tsq.tsq_evolve_passes(h, 8) == (8, False)
+        assert tsq.tsq_evolve_passes(h, 7) == (8, False)  # one step per pass, then the closing pass
+        assert tsq.tsq_evolve_passes(h, 8) == (9, True)
+        assert tsq.tsq_evolve_passes(h, 0) == (0, False)
         lib = tsq.load_library()
         assert lib.tsq_set_potential_td(h, 16, 16, 256, 1 << 30, None) == -7
     finally:
