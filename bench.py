@@ -461,7 +461,7 @@ def main() -> int:
                          "512^3 packet in a harmonic well, 100 steps")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--fifo-seconds", type=float, default=10.0)
-    ap.add_argument("--block-steps", type=int, default=24)
+    ap.add_argument("--block-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path "

@@ -33,7 +33,8 @@ import torch
 import paper_1208_2407_amd as tsq
 from paper_1208_2407_amd import workloads as wl
 
-SCHEDULES = {"c64": (6, 0, 1, 2), "c128": (6, 0, 1, 2)}
+# 5 steps per pass, LDS phase ring, for both dtypes; blocks of 20 steps are 4 passes
+SCHEDULES = {"c64": (5, 0, 1, 2), "c128": (5, 0, 1, 2)}
 
 
 def request_bytes(p: wl.Problem) -> int:
@@ -74,7 +75,7 @@ class Stats:
 
 
 class Server:
-    def __init__(self, hbm_budget: int = 96 << 30, block_steps: int = 24,
+    def __init__(self, hbm_budget: int = 96 << 30, block_steps: int = 20,
                  max_in_flight: int = 2, keep_results: bool = False, device="cuda"):
         self.budget = int(hbm_budget)
         self.block = int(block_steps)
