@@ -138,7 +138,6 @@ hipError_t launch_td_table(const double* V0, const double* W, void* table, long 
                            double dt, double eps0, double hbar, hipStream_t s);
 hipError_t launch_pass(int dtype, const PassDesc& d, hipStream_t s);
 hipError_t launch_pass3(int dtype, const Pass3Desc& d, hipStream_t s);
-int march3_blocks_per_cu(int dtype, bool close);
 hipError_t launch_observables3(int dtype, const void* psi, const double* V, int nx, int ny, int nz,
                                double Jx, double Jy, double Jz, double eps0, double* partial,
                                int nblocks, double* result, hipStream_t s);

@@ -324,14 +324,6 @@ hipError_t launch_observables3(int dtype, const void* psi, const double* V, int 
     return hipGetLastError();
 }
 
-int march3_blocks_per_cu(int dtype, bool close) {
-    const void* f = dtype == 1 ? march3_ptr_c128(close) : march3_ptr_c64(close);
-    int n = 0;
-    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kWaveSize * kWaves3, 0) != hipSuccess)
-        return 0;
-    return n;
-}
-
 template <class R>
 static hipError_t launch3_with(const void* f, const Pass3Desc& d, hipStream_t s) {
     const int K = 1;
