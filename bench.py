@@ -30,15 +30,19 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+# The sources the benchmarked 2D march kernels and their launches are built from
+# (the 3D and time-dependent paths live in files of their own).
+KERNEL_SOURCES = ("tsq_march.hpp", "tsq_internal.h", "tsq_kernels.hip", "march_c64_single.hip",
+                  "march_c128_single.hip")
+
+
 def kernel_hash() -> str:
-    """sha256[:16] of the device sources (csrc/*.hip, *.hpp, *.h)."""
-    import glob
+    """sha256[:16] of the sources of the benchmarked march kernels."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1208_2407_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))
-                    + glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -19,6 +19,7 @@
 
 #include "../../include/tsq.h"
 #include "tsq_internal.h"
+#include "tsq_internal3.h"
 
 // One kind of second-order sub-step: its duration, rotation coefficients and
 // phase table.  Order 2 has one kind (dt); order 4 has two (p dt, (1-4p) dt).

@@ -17,6 +17,7 @@
 // per side, like the 2D halo).
 #pragma once
 
+#include "tsq_internal3.h"
 #include "tsq_march.hpp"
 
 namespace tsq {
