@@ -590,6 +590,12 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     int wslot = 0;  // LDS slot receiving the phase of pair j-1 at the end of iteration j
     int q = rev ? tstart + 1 : tstart - 1;  // pair stage 0 completes this iteration
     const int qend = rev ? q - nit : q + nit;  // ... one past the last iteration
+    // Stage k in iteration i (0-based) completes the pair 1+k behind the one
+    // loaded, which reaches the region the stored pairs depend on (K-k pairs
+    // of halo ahead of them along the march, one more for the odd boundary)
+    // only from i = 2k+1 on: earlier runs fill the pipeline with values no
+    // stored site depends on, and are skipped (a wavefront-uniform branch).
+    int it = 0;
     load_psi(home[0]);
     // One march iteration with static home indices (u = j mod NH).
     auto iteration = [&](auto U) {
@@ -601,6 +607,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         load_phase(ph[u % NP]);
         static_for<K>([&](auto KK) {
             constexpr int k = decltype(KK)::value;
+            if (it > 2 * k)
             pipeline_stage<S, K, CLOSED, TD, R, SPL, PT>(
                 k, home[(u - 1 - k + 2 * NH) % NH], home[(u - k + 2 * NH) % NH], a, xm,
                 rev ? q + k : q - k, rev, [&](int kk) {
@@ -621,6 +628,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         });
         store_out(home[(u - K + 2 * NH) % NH]);
         q += rev ? -1 : 1;
+        ++it;
         if constexpr (LDS && S > 1) {
             const PhasePair<PT, SPL>& p0 = ph[(u - 1 + 2 * NP) % NP];
 #pragma unroll
