@@ -3,8 +3,10 @@
 A schedule is (steps_per_pass, segment_rows, pairs_per_lane, phase_store) of
 ``tsq_plan_set_schedule``.  Every schedule gives bitwise identical results, so
 the tuner only times: it evolves a scratch copy of the state for a few passes
-under each candidate (HIP events on the current stream), keeps the fastest,
-and caches the choice per (device architecture, dtype, mesh) in a JSON file
+under each candidate (HIP events on the current stream), keeps the fastest
+(among schedules within ``TIE`` of the fastest, the one with the fewest steps
+per pass: it computes fewer redundant halo sites for the same speed), and
+caches the choice per (device architecture, dtype, mesh) in a JSON file
 (``$TSQ_AUTOTUNE_CACHE``, default ``~/.cache/tsq/autotune.json``).
 """
 from __future__ import annotations
@@ -24,6 +26,10 @@ DEFAULT_CANDIDATES: List[Schedule] = (
     + [(S, 0, 1, store) for S in (2, 3, 4) for store in (1, 2)]
     + [(S, 0, 1, 2) for S in (5, 6)]
 )
+
+
+# relative time difference below which two schedules count as equally fast
+TIE = 0.01
 
 
 def cache_path() -> str:
@@ -83,6 +89,14 @@ def time_schedule(plan, psi, schedule: Schedule, steps: int, repeats: int = 2) -
     return best
 
 
+def pick(timed: List[Tuple[float, Schedule]], tie: float = TIE) -> Schedule:
+    """The schedule to keep from (milliseconds, schedule) pairs: the fewest
+    steps per pass among those within `tie` of the fastest (then the fastest)."""
+    fastest = min(ms for ms, _ in timed)
+    near = [(c[0], ms, c) for ms, c in timed if ms <= fastest * (1.0 + tie)]
+    return min(near)[2]
+
+
 def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: int = 120,
          use_cache: bool = True, log=None) -> Tuple[Schedule, Dict[str, float]]:
     """Pick the fastest schedule for this plan's mesh and dtype; set it on the plan.
@@ -99,16 +113,16 @@ def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: i
         return sched, db[key].get("table", {})
     scratch = psi.clone()
     table: Dict[str, float] = {}
-    best: Optional[Schedule] = None
+    timed: List[Tuple[float, Schedule]] = []
     for cand in (candidates or DEFAULT_CANDIDATES):
         ms = time_schedule(plan, scratch, cand, steps)
         table[",".join(map(str, cand))] = ms
+        timed.append((ms, tuple(cand)))
         if log:
             log(f"autotune {key} S={cand[0]} seg={cand[1]} ppl={cand[2]} store={cand[3]}: "
                 f"{ms:.3f} ms")
-        if best is None or ms < table[",".join(map(str, best))]:
-            best = cand
     del scratch
+    best = pick(timed)
     plan.set_schedule(*best)
     if use_cache:
         db[key] = {"schedule": list(best), "table": table, "steps": steps}
