@@ -299,6 +299,60 @@ def profile_mode(p, psi0, V, args) -> int:
     return 0
 
 
+def sweep_mode(p, psi0, V, args) -> int:
+    """Every candidate schedule (the tuner's, plus 7 and 8 steps per pass) for
+    exactly --profile-passes passes after a warm-up, each timed with HIP events
+    on the current stream; one JSON line per dtype and schedule.  Run under
+    rocprofv3 --pmc it also gives the HBM counters of every schedule."""
+    import torch
+    import paper_1208_2407_amd as tsq
+    from paper_1208_2407_amd import autotune
+
+    cands = list(autotune.DEFAULT_CANDIDATES) + [(7, 0, 1, 2), (8, 0, 1, 2)]
+    stream = torch.cuda.current_stream()
+    # reference copy of known size (1 GiB read + 1 GiB written) to scale the counters
+    src = torch.empty(2**27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    for d in args.dtypes.split(","):
+        tdt = torch.complex128 if d == "c128" else torch.complex64
+        elem = 16 if d == "c128" else 8
+        alg = p.nx * p.ny * (2 * elem + 16)
+        for sched in cands:
+            psi = psi0.to(tdt).clone()
+            plan = tsq.Plan(p.nx, p.ny, p.dt, d, device=psi.device)
+            plan.set_potential(V)
+            plan.set_schedule(*sched)
+            S = sched[0]
+            plan.evolve(psi, 2 * S)
+            steps = S * args.profile_passes
+            passes = plan.passes(steps)[0]
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            plan.evolve(psi, steps)
+            e1.record(stream)
+            e1.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3
+            pass_s = sec / passes
+            print(json.dumps({"sweep": True, "dtype": d, "schedule": list(sched),
+                              "kernel_hash": kernel_hash(), "mesh": [p.nx, p.ny],
+                              "steps": steps, "passes": passes,
+                              "avg_pass_us": round(pass_s * 1e6, 2),
+                              "us_per_step": round(sec / steps * 1e6, 3),
+                              "site_steps_per_s": p.nx * p.ny * steps / sec,
+                              "algorithmic_bytes_per_launch": alg,
+                              "frac": round(alg / pass_s / 1e9 / HBM_PEAK_GBS, 4),
+                              "eff_frac_one_pass_per_step": round(
+                                  p.nx * p.ny * steps / sec * alg / (p.nx * p.ny) / 1e9
+                                  / HBM_PEAK_GBS, 3)}), flush=True)
+            del psi, plan
+    return 0
+
+
 def run_batch(args) -> dict:
     """512 independent complex64 problems (sides log-uniform in [64, 1024], rounded to
     even; own potential, packets and dt), 500 steps each: one batched call (captured
@@ -450,7 +504,8 @@ def main() -> int:
     ap.add_argument("--profile-passes", type=int, default=0,
                     help="counter-collection mode: per dtype run exactly this many fused "
                          "passes under --schedule, plus one device copy of 1 GiB (known "
-                         "bytes) to scale the HBM counters; prints a short JSON and exits")
+                         "bytes) to scale the HBM counters; prints a short JSON and exits. "
+                         "With --schedule sweep: every candidate schedule, each timed")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=400)
@@ -552,6 +607,8 @@ def main() -> int:
     V = wl.potential(p, device="cuda")
     torch.cuda.synchronize()
 
+    if args.profile_passes and args.schedule == "sweep":
+        return sweep_mode(p, psi0, V, args)
     if args.profile_passes:
         return profile_mode(p, psi0, V, args)
 
