@@ -131,8 +131,9 @@ typedef struct {
                                 launch is one round of resident wavefronts */
     int32_t pairs_per_lane;  /* x-pairs held by each lane: 1 or 2, 0 = default (1) */
     int32_t phase_store;     /* phase factors in flight: 1 = registers (steps_per_pass
-                                <= 4), 2 = LDS (pairs_per_lane 1), 0 = default
-                                (registers up to 4 steps per pass, else LDS) */
+                                <= 6, <= 4 with pairs_per_lane 2), 2 = LDS
+                                (pairs_per_lane 1), 0 = default (registers up to 6
+                                steps per pass, else LDS) */
 } tsq_schedule;
 
 /* Set the plan's schedule (host only).  Zero fields take their defaults;

@@ -23,8 +23,7 @@ Schedule = Tuple[int, int, int, int]
 # instruction cache); both stay available through tsq_plan_set_schedule.
 DEFAULT_CANDIDATES: List[Schedule] = (
     [(1, 0, 1, 1)]
-    + [(S, 0, 1, store) for S in (2, 3, 4) for store in (1, 2)]
-    + [(S, 0, 1, 2) for S in (5, 6)]
+    + [(S, 0, 1, store) for S in (2, 3, 4, 5, 6) for store in (1, 2)]
 )
 
 

@@ -91,6 +91,8 @@ bool resolve_schedule(const tsq_schedule& in, tsq_schedule& out) {
     if (out.phase_store == 0) out.phase_store = out.steps_per_pass <= tsq::kMaxRegSteps ? 1 : 2;
     if (out.pairs_per_lane == 0) out.pairs_per_lane = 1;
     if (out.phase_store == 1 && out.steps_per_pass > tsq::kMaxRegSteps) return false;
+    if (out.phase_store == 1 && out.pairs_per_lane == 2 && out.steps_per_pass > tsq::kMaxRegSteps2)
+        return false;
     if (out.phase_store == 2 && out.pairs_per_lane != 1) return false;
     return true;
 }
@@ -641,8 +643,10 @@ int tsq_plan_set_schedule(tsq_plan* plan, const tsq_schedule* sc) {
     if (!resolve_schedule(*sc, r))
         return fail(TSQ_ERR_ARG,
                     "no kernel for steps_per_pass %d, pairs_per_lane %d, phase_store %d "
-                    "(registers hold at most %d steps; LDS needs 1 pair per lane)",
-                    r.steps_per_pass, r.pairs_per_lane, r.phase_store, tsq::kMaxRegSteps);
+                    "(registers hold at most %d steps, %d with 2 pairs per lane; LDS needs 1 "
+                    "pair per lane)",
+                    r.steps_per_pass, r.pairs_per_lane, r.phase_store, tsq::kMaxRegSteps,
+                    tsq::kMaxRegSteps2);
     if (plan->p.bc == TSQ_BC_CLOSED && r.pairs_per_lane != 1)
         return fail(TSQ_ERR_ARG, "closed meshes run with 1 pair per lane");
     plan->sched = r;

@@ -33,7 +33,8 @@ struct PassDesc {
 };
 
 constexpr int kMaxSteps = 8;     // deepest fusion (phase ring in LDS)
-constexpr int kMaxRegSteps = 4;  // deepest fusion with the phase ring in registers
+constexpr int kMaxRegSteps = 6;  // deepest fusion with the phase ring in registers
+constexpr int kMaxRegSteps2 = 4; // ... with two x-pairs per lane
 constexpr int kMaxTdSteps = 4;   // deepest fusion with a time-dependent potential
 constexpr int kWaveSize = 64;
 constexpr int kWavesPerBlock = 4;

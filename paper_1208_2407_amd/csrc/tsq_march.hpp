@@ -688,11 +688,12 @@ march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
     }
 }
 
-// Instances: periodic register ring for 1..4 steps per pass (1 or 2 pairs
-// per lane), periodic LDS ring for 1..kMaxSteps (1 pair per lane), single
-// and batched; closed meshes: both rings with 1 pair per lane, single only;
-// time-dependent potentials (periodic): both rings, 1 pair per lane, at most
-// kMaxTdSteps steps per pass, single only.
+// Instances: periodic register ring for 1..kMaxRegSteps steps per pass with
+// 1 pair per lane, 1..kMaxRegSteps2 with 2, periodic LDS ring for
+// 1..kMaxSteps (1 pair per lane), single and batched; closed meshes: both
+// rings with 1 pair per lane, single only; time-dependent potentials
+// (periodic): both rings, 1 pair per lane, at most kMaxTdSteps steps per
+// pass, single only.
 enum class Variant { Single, Batch, Closed, TimeDep };
 
 template <class T, int S, bool LAST, int PPL, bool LDS, Variant V>
@@ -728,8 +729,10 @@ const void* pick_variant(int steps, int ppl, bool lds) {
     }
     if (ppl == 2) {
         if constexpr (V == Variant::Closed || V == Variant::TimeDep) return nullptr;
-        return pick_steps<T, V, LAST, 2, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
+        return pick_steps<T, V, LAST, 2, false>(steps, std::make_integer_sequence<int, kMaxRegSteps2>());
     }
+    if constexpr (V == Variant::TimeDep)
+        return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxTdSteps>());
     return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
 }
 

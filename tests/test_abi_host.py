@@ -84,11 +84,14 @@ def test_schedule_validation():
         assert tsq.tsq_plan_get_schedule(h).as_tuple() == (3, 64, 2, 1)
         tsq.tsq_plan_set_schedule(h, sched(0, 0, 0, 0))
         assert tsq.tsq_plan_get_schedule(h).as_tuple() == (4, 0, 1, 1)
+        tsq.tsq_plan_set_schedule(h, sched(6, 0, 0, 0))
+        assert tsq.tsq_plan_get_schedule(h).as_tuple() == (6, 0, 1, 1)
         tsq.tsq_plan_set_schedule(h, sched(7, 0, 0, 0))
         assert tsq.tsq_plan_get_schedule(h).as_tuple() == (7, 0, 1, 2)
         before = tsq.tsq_plan_get_schedule(h).as_tuple()
         for bad in ((-1, 0, 0, 0), (9, 0, 0, 0), (2, 7, 0, 0), (2, -2, 0, 0), (1, 0, 3, 0),
-                    (1, 0, 0, 3), (5, 0, 0, 1), (2, 0, 2, 2), (8, 0, 2, 0)):
+                    (1, 0, 0, 3), (7, 0, 0, 1), (5, 0, 2, 1), (5, 0, 2, 0), (2, 0, 2, 2),
+                    (8, 0, 2, 0)):
             with pytest.raises(tsq.TsqError) as ei:
                 tsq.tsq_plan_set_schedule(h, sched(*bad))
             assert ei.value.status == -1

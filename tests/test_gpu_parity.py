@@ -43,8 +43,10 @@ SHAPES = [(2, 2), (4, 6), (130, 66), (300, 258), (258, 300), (66, 1030)]
 def variants(S):
     """(pairs_per_lane, phase_store) kernel variants built for S steps per pass."""
     v = [(1, 2)]
+    if S <= 6:
+        v += [(1, 1)]
     if S <= 4:
-        v += [(1, 1), (2, 1)]
+        v += [(2, 1)]
     return v
 
 
@@ -216,7 +218,7 @@ def test_closed_meshes(shape, S, dtype):
     nx, ny = shape
     psi0 = wl.random_state(nx, ny, 50 + nx)
     V = wl.random_potential(nx, ny, 51 + ny, scale=0.5)
-    stores = (1, 2) if S <= 4 else (2,)
+    stores = (1, 2) if S <= 6 else (2,)
     for steps in (1, 6):
         want = oracle_evolve(psi0, V, 0.11, steps, dtype, bc="closed", **ANISO)
         for store in stores:

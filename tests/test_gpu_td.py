@@ -70,7 +70,7 @@ def test_td_schedule_and_call_split_do_not_change_a_bit(dtype):
     ref = gpu_evolve_td(psi0, V0, W, f, 0.09, dtype, steps_per_pass=1, segment_rows=2, phase_store=1)
     for S in range(1, 9):
         for seg in (2, 6, 0):
-            for store in ((1, 2) if S <= 4 else (2,)):
+            for store in ((1, 2) if S <= 6 else (2,)):
                 got = gpu_evolve_td(psi0, V0, W, f, 0.09, dtype, steps_per_pass=S, segment_rows=seg,
                                     phase_store=store)
                 assert np.array_equal(got, ref), (S, seg, store)
