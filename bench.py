@@ -383,15 +383,17 @@ def run_batch(args) -> dict:
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    # batch schedule: a short search over steps per pass (LDS ring, one pair per lane)
+    # batch schedule: a short search over steps per pass and phase ring (one pair per lane)
     best = None
-    for S in ([int(args.schedule.split(",")[0])] if args.schedule else (3, 4, 5, 6)):
-        sched = (S, 0, 1, 2)
+    cands = ([tuple(int(v) for v in args.schedule.split(","))] if args.schedule
+             else [(S, 0, 1, st) for S in (3, 4, 5, 6) for st in (1, 2)])
+    for sched in cands:
         psis = [x.clone() for x in psi0s]
         bt = tsq.Batch(plans, psis, steps, sched)
         bt.launch(use_graph=True)
         t = timed(lambda: bt.launch(use_graph=True), 1)
-        log(f"batch: S={S}: {t * 1e3:.1f} ms per call ({bt.info()[0]} launches)")
+        log(f"batch: S={sched[0]} store={sched[3]}: {t * 1e3:.1f} ms per call "
+            f"({bt.info()[0]} launches)")
         if best is None or t < best[0]:
             best = (t, sched)
         del bt, psis

@@ -33,8 +33,8 @@ import torch
 import paper_1208_2407_amd as tsq
 from paper_1208_2407_amd import workloads as wl
 
-# 5 steps per pass, LDS phase ring, for both dtypes; blocks of 20 steps are 4 passes
-SCHEDULES = {"c64": (5, 0, 1, 2), "c128": (5, 0, 1, 2)}
+# 5 steps per pass, register phase ring, for both dtypes; blocks of 20 steps are 4 passes
+SCHEDULES = {"c64": (5, 0, 1, 1), "c128": (5, 0, 1, 1)}
 
 
 def request_bytes(p: wl.Problem) -> int:
