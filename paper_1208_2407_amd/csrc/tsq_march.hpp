@@ -102,57 +102,75 @@ __device__ __forceinline__ void apply_phase(float& re, float& im, const float4 p
 // written from the mathematics: Cody and Waite's additive reduction
 // r = x - k pi/2, with pi/2 split into C1 (the double nearest pi/2) and C2
 // (the double nearest pi/2 - C1) and the product k C1 exact inside an FMA;
-// the Taylor series of sin and cos on |r| <= pi/4 through r^17 and r^16 (the
-// first omitted terms are below 1e-19); the quadrant k mod 4.  A few ulp for
-// |x| < 2^40.
+// the Taylor series of sin and cos on |r| <= pi/4; the quadrant k mod 4.
+// k comes from adding 1.5 * 2^52 inside the FMA that forms x * 2/pi: the sum
+// then holds round(x * 2/pi) in the low bits of its significand (|x| < 2^50),
+// and the quadrant's sign is one exclusive or on the sign bit.
+// FULL: series through r^17 and r^16 (first omitted terms below 1e-19; a few
+// ulp for |x| < 2^40), for complex128.  Otherwise through r^13 and r^14 (first
+// omitted terms below 2.1e-14 and 1.1e-15), for complex64, whose state keeps
+// 24 bits.
+template <bool FULL>
 __device__ __forceinline__ void sincos_td(double x, double& sn, double& cs) {
     const double C1 = 0x1.921fb54442d18p+0;   // pi/2 rounded to double
     const double C2 = 0x1.1a62633145c07p-54;  // pi/2 - C1 rounded to double
-    const double k = rint(x * 0x1.45f306dc9c883p-1);  // x * (2/pi)
+    const double shifter = 0x1.8p52;          // 1.5 * 2^52: unit in the last place 1
+    const double t = mad(x, 0x1.45f306dc9c883p-1, shifter);  // x * (2/pi) + shifter
+    const double k = t - shifter;                              // exact
+    const unsigned q = (unsigned)__double2loint(t);           // k mod 4 in bits 0..1
     double r = mad(-k, C1, x);
     r = mad(-k, C2, r);
     const double r2 = r * r;
-    // sin r = r + r^3 (-1/3! + r^2/5! - ... + r^14/17!)
-    double ps = 1.0 / 355687428096000.0;
-    ps = mad(ps, r2, -1.0 / 1307674368000.0);
-    ps = mad(ps, r2, 1.0 / 6227020800.0);
-    ps = mad(ps, r2, -1.0 / 39916800.0);
-    ps = mad(ps, r2, 1.0 / 362880.0);
-    ps = mad(ps, r2, -1.0 / 5040.0);
-    ps = mad(ps, r2, 1.0 / 120.0);
-    ps = mad(ps, r2, -1.0 / 6.0);
+    // sin r = r + r^3 (-1/3! + r^2/5! - ...), cos r = 1 + r^2 (-1/2! + r^2/4! - ...)
+    double ps, pc;
+    if constexpr (FULL) {
+        ps = 1.0 / 355687428096000.0;                  // 1/17!
+        ps = mad(ps, r2, -1.0 / 1307674368000.0);     // 1/15!
+        ps = mad(ps, r2, 1.0 / 6227020800.0);         // 1/13!
+        pc = 1.0 / 20922789888000.0;                   // 1/16!
+        pc = mad(pc, r2, -1.0 / 87178291200.0);       // 1/14!
+    } else {
+        ps = 1.0 / 6227020800.0;
+        pc = -1.0 / 87178291200.0;
+    }
+    ps = mad(ps, r2, -1.0 / 39916800.0);   // 1/11!
+    ps = mad(ps, r2, 1.0 / 362880.0);      // 1/9!
+    ps = mad(ps, r2, -1.0 / 5040.0);       // 1/7!
+    ps = mad(ps, r2, 1.0 / 120.0);         // 1/5!
+    ps = mad(ps, r2, -1.0 / 6.0);          // 1/3!
     const double sr = mad(r * r2, ps, r);
-    // cos r = 1 + r^2 (-1/2! + r^2/4! - ... + r^14/16!)
-    double pc = 1.0 / 20922789888000.0;
-    pc = mad(pc, r2, -1.0 / 87178291200.0);
-    pc = mad(pc, r2, 1.0 / 479001600.0);
-    pc = mad(pc, r2, -1.0 / 3628800.0);
-    pc = mad(pc, r2, 1.0 / 40320.0);
-    pc = mad(pc, r2, -1.0 / 720.0);
-    pc = mad(pc, r2, 1.0 / 24.0);
-    pc = mad(pc, r2, -0.5);
+    pc = mad(pc, r2, 1.0 / 479001600.0);   // 1/12!
+    pc = mad(pc, r2, -1.0 / 3628800.0);    // 1/10!
+    pc = mad(pc, r2, 1.0 / 40320.0);       // 1/8!
+    pc = mad(pc, r2, -1.0 / 720.0);        // 1/6!
+    pc = mad(pc, r2, 1.0 / 24.0);          // 1/4!
+    pc = mad(pc, r2, -0.5);                // 1/2!
     const double cr = mad(r2, pc, 1.0);
-    // quadrant q: (sin, cos) of x = (sr, cr), (cr, -sr), (-sr, -cr), (-cr, sr)
-    const int q = (int)((long long)k & 3);
-    const double a = (q & 1) ? cr : sr;
-    const double b = (q & 1) ? sr : cr;
-    sn = (q & 2) ? -a : a;
-    cs = ((q + 1) & 2) ? -b : b;
+    // (sin, cos) of x = (sr, cr), (cr, -sr), (-sr, -cr), (-cr, sr) for q = 0..3:
+    // swap on odd q; sin negative for q = 2, 3, cos for q = 1, 2
+    const bool odd = (q & 1u) != 0;
+    const double a = odd ? cr : sr;
+    const double b = odd ? sr : cr;
+    const int ssign = (int)((q << 30) & 0x80000000u);
+    const int csign = (int)(((q + 1u) << 30) & 0x80000000u);
+    sn = __hiloint2double(__double2hiint(a) ^ ssign, __double2loint(a));
+    cs = __hiloint2double(__double2hiint(b) ^ csign, __double2loint(b));
 }
 
 // Potential phase of step n under V0 + f_n W: tw = (theta0, w) of the site,
-// g = f_n; the factor exp(-i (theta0 + g w)) is formed in FP64 and applied as
-// the static tables are (complex64: split into hi + lo floats).
+// g = f_n; the factor exp(-i (theta0 + g w)) is formed in FP64 and applied in
+// FP64 (complex64: to the state widened to FP64, the product rounded once).
 __device__ __forceinline__ void apply_phase_td(double& re, double& im, const double2 tw, double g) {
     double sn, cs;
-    sincos_td(mad(g, tw.y, tw.x), sn, cs);
+    sincos_td<true>(mad(g, tw.y, tw.x), sn, cs);
     apply_phase(re, im, make_double2(cs, -sn));
 }
 __device__ __forceinline__ void apply_phase_td(float& re, float& im, const double2 tw, double g) {
     double sn, cs;
-    sincos_td(mad(g, tw.y, tw.x), sn, cs);
-    const float hr = (float)cs, hi = (float)(-sn);
-    apply_phase(re, im, make_float4(hr, hi, (float)(cs - (double)hr), (float)(-sn - (double)hi)));
+    sincos_td<false>(mad(g, tw.y, tw.x), sn, cs);
+    const double r = re, i = im;
+    re = (float)mad(r, cs, i * sn);    // (r + i i)(cs - i sn)
+    im = (float)mad(i, cs, -(r * sn));
 }
 
 // ------------------------------------------------------------------ dtype traits
