@@ -126,7 +126,7 @@ int tsq_workspace_size(const tsq_plan* plan, size_t* bytes);
  * identical across schedules; only speed changes. */
 typedef struct {
     int32_t steps_per_pass;  /* time steps per read+write of psi in device memory:
-                                1..8, 0 = default (4) */
+                                1..8, 0 = default (5) */
     int32_t segment_rows;    /* rows marched by one wavefront: even, 0 = sized so one
                                 launch is one round of resident wavefronts */
     int32_t pairs_per_lane;  /* x-pairs held by each lane: 1 or 2, 0 = default (1) */

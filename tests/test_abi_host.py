@@ -83,7 +83,7 @@ def test_schedule_validation():
         tsq.tsq_plan_set_schedule(h, sched(3, 64, 2, 1))
         assert tsq.tsq_plan_get_schedule(h).as_tuple() == (3, 64, 2, 1)
         tsq.tsq_plan_set_schedule(h, sched(0, 0, 0, 0))
-        assert tsq.tsq_plan_get_schedule(h).as_tuple() == (4, 0, 1, 1)
+        assert tsq.tsq_plan_get_schedule(h).as_tuple() == (5, 0, 1, 1)
         tsq.tsq_plan_set_schedule(h, sched(6, 0, 0, 0))
         assert tsq.tsq_plan_get_schedule(h).as_tuple() == (6, 0, 1, 1)
         tsq.tsq_plan_set_schedule(h, sched(7, 0, 0, 0))
