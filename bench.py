@@ -36,14 +36,42 @@ KERNEL_SOURCES = ("tsq_march.hpp", "tsq_internal.h", "tsq_kernels.hip", "march_c
                   "march_c128_single.hip")
 
 
+def code_text(src: str) -> str:
+    """C++ source without its comments, whitespace runs collapsed to one space:
+    what the compiler sees, so an edit of a comment keeps the hash."""
+    out = []
+    i, n = 0, len(src)
+    while i < n:
+        c = src[i]
+        if c == "/" and src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif c == "/" and src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_hash() -> str:
-    """sha256[:16] of the sources of the benchmarked march kernels."""
+    """sha256[:16] of the code (comments and layout removed) of the sources of the
+    benchmarked march kernels."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1208_2407_amd", "csrc")
     for name in KERNEL_SOURCES:
         h.update(name.encode())
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -359,11 +359,11 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // k-1 (or just loaded, for k = 0).  Stage k applies the odd factors on the
 // boundary of the two (o's G row and n's F row; n's G row gets the same
 // factors in stage k+1, where n is the older pair), then, for k < S, step
-// k+1's even factors and the potential phase on o.  Stage K-1 = S of the last pass applies only the
-// closing odd factors.  With a time-dependent potential (TD) the phase pair
-// holds (theta0, w) per site and stage k forms step k's factor from a.g[k].
-// Closed meshes skip the y-pairs that cross a wall
-// (`qk` is the pair stage k completes; a wavefront-uniform test).
+// k+1's even factors and the potential phase on o.  Stage K-1 = S of the
+// last pass applies only the closing odd factors.  With a time-dependent
+// potential (TD) the phase pair holds (theta0, w) per site and stage k forms
+// step k's factor from a.g[k].  Closed meshes skip the y-pairs that cross a
+// wall (`qk` is the pair stage k completes; a wavefront-uniform test).
 template <int S, int K, bool CLOSED, bool TD, class R, int SPL, class PT, class PhaseFn>
 __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
                                                const MarchArgs<R>& a,
