@@ -76,16 +76,17 @@ def kernel_hash() -> str:
 
 
 def committed_traffic(dtype: str, schedule) -> float | None:
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were
-    taken on this exact kernel source and schedule; else None."""
+    """HBM bytes per launch from the committed rocprofv3 counter runs (keyed by
+    kernel code hash, dtype and schedule "S,seg,ppl,store"), if they were taken on
+    this exact kernel code and schedule; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             db = json.load(f)
     except (OSError, ValueError):
         return None
-    e = db.get(kernel_hash(), {}).get(dtype)
-    if not e or list(e.get("schedule", [])) != list(schedule):
+    e = db.get(kernel_hash(), {}).get(dtype, {}).get(",".join(str(int(v)) for v in schedule))
+    if not e:
         return None
     return float(e["bytes_per_launch"])
 
