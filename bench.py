@@ -75,17 +75,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(dtype: str, schedule) -> float | None:
+def committed_traffic(dtype: str, schedule, nx: int, ny: int) -> float | None:
     """HBM bytes per launch from the committed rocprofv3 counter runs (keyed by
-    kernel code hash, dtype and schedule "S,seg,ppl,store"), if they were taken on
-    this exact kernel code and schedule; else None."""
+    kernel code hash, mesh "NXxNY", dtype and schedule "S,seg,ppl,store"), if they
+    were taken on this exact kernel code, mesh and schedule; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             db = json.load(f)
     except (OSError, ValueError):
         return None
-    e = db.get(kernel_hash(), {}).get(dtype, {}).get(",".join(str(int(v)) for v in schedule))
+    e = (db.get(kernel_hash(), {}).get(f"{nx}x{ny}", {}).get(dtype, {})
+         .get(",".join(str(int(v)) for v in schedule)))
     if not e:
         return None
     return float(e["bytes_per_launch"])
@@ -137,7 +138,7 @@ def run_dtype(dtype: str, p, psi0, V, args):
     alg_bytes = p.nx * p.ny * (2 * elem + 16)   # read psi, write psi, read phase table
     launch_s = evolve_ms * 1e-3 / (args.steps * passes)
     achieved = alg_bytes / launch_s / 1e9
-    traffic = committed_traffic(dtype, sched)
+    traffic = committed_traffic(dtype, sched, p.nx, p.ny)
     # one pass per step would need the same bytes every step: site-steps/s times those
     # bytes over the peak says how far fusion takes the solve past that roofline (> 1)
     eff_frac = (site_steps / wall) * (2 * elem + 16) / (HBM_PEAK_GBS * 1e9)
