@@ -35,6 +35,7 @@ def test_mesh32768_complex64_crops():
                       psi[y0:y0 + W, x0:x0 + W].cpu().numpy().astype(np.complex128),
                       V[y0:y0 + W, x0:x0 + W].cpu().numpy()))
     plan = tsq.Plan(n, n, p.dt, "c64")
+    plan.set_schedule(6, 0, 1, 1)   # the schedule the tuner picks for this mesh in bench.py
     plan.set_potential(V)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -138,12 +138,17 @@ def test_observables_match_oracle(shape, dtype):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_mesh4096_sampled_windows(dtype):
     """Full 4096^2 mesh of the packets-and-bumps recipe in the benchmark's launch
-    configuration, 50 steps; sampled 256^2 windows checked against oracle runs on the
-    window plus its light cone (2N+1 sites per side, rounded up to an even margin)."""
+    configurations (5 and 6 steps per pass with the register phase ring, one round of
+    wavefronts: the schedules the tuner picks there), 50 steps; sampled 256^2 windows
+    checked against oracle runs on the window plus its light cone (2N+1 sites per side,
+    rounded up to an even margin)."""
     p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 50, dtype)
     psi0 = wl.initial_state(p).numpy()
     V = wl.potential(p).numpy()
-    got = gpu_evolve(psi0, V, p.dt, p.steps, dtype)
+    runs = [gpu_evolve(psi0, V, p.dt, p.steps, dtype, steps_per_pass=S, phase_store=1)
+            for S in (5, 6)]
+    assert np.array_equal(runs[0], runs[1])
+    got = runs[0]
     m = 2 * p.steps + 2
     h = w = 256
     ref_in = as_input(psi0, dtype)
