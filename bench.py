@@ -156,6 +156,8 @@ def run_dtype(dtype: str, p, psi0, V, args):
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "traffic_GBps": round(traffic / launch_s / 1e9, 1) if traffic else None,
+                     "traffic_frac": (round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic else None),
                      "eff_frac_one_pass_per_step": round(eff_frac, 3),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel": "march_kernel", "avg_launch_us": round(launch_s * 1e6, 2)},
