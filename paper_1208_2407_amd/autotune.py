@@ -47,8 +47,8 @@ def _library_stamp() -> str:
         return "?"
 
 
-def _key(arch: str, dtype: str, nx: int, ny: int, order: int = 2) -> str:
-    return f"{arch}|{dtype}|{nx}x{ny}|o{order}|{_library_stamp()}"
+def _key(arch: str, dtype: str, nx: int, ny: int, order: int = 2, bc: int = 0) -> str:
+    return f"{arch}|{dtype}|{nx}x{ny}|o{order}|bc{bc}|{_library_stamp()}"
 
 
 def _load() -> Dict[str, dict]:
@@ -104,7 +104,8 @@ def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: i
     the timing table {"S,seg,ppl": ms}."""
     import torch
     arch = torch.cuda.get_device_properties(psi.device).gcnArchName.split(":")[0]
-    key = _key(arch, plan.dtype, plan.problem.nx, plan.problem.ny, plan.problem.order)
+    key = _key(arch, plan.dtype, plan.problem.nx, plan.problem.ny, plan.problem.order,
+               plan.problem.bc)
     db = _load() if use_cache else {}
     if use_cache and key in db and len(db[key].get("schedule", [])) == 4:
         sched = tuple(db[key]["schedule"])
