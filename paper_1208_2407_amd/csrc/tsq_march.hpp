@@ -227,8 +227,10 @@ __device__ __forceinline__ void store_pair(void* base, long long off, const Row<
 
 // Which x-pairs of a lane exist.  Periodic meshes have every pair (the
 // struct is empty and the checks vanish); closed meshes have no pair that
-// crosses a wall: a lane whose pair reaches outside [0, nx) keeps those
-// sites unrotated (they hold zeros and are never stored).
+// crosses a wall: such a pair is rotated with zero coefficients (s = d = 0
+// leaves both sites exactly as they were, up to the sign of a zero), so the
+// sites inside keep their values and whatever a site outside the mesh holds
+// never reaches one inside.
 template <int PPL, bool CLOSED>
 struct XPairs {
     bool even[PPL];      // (x, x+1) of pair p
@@ -238,9 +240,13 @@ struct XPairs {
 template <int PPL>
 struct XPairs<PPL, false> {};
 
-template <class R>
-__device__ __forceinline__ void keep_old(bool ok, R& v, R old) {
-    v = ok ? v : old;
+// The coefficient of a pair that exists, else 0.
+template <bool CLOSED, class R>
+__device__ __forceinline__ R pair_coef(bool exists, R c) {
+    if constexpr (CLOSED)
+        return exists ? c : R(0);
+    else
+        return (void)exists, c;
 }
 
 // Even x-pairs: inside the lane.
@@ -248,16 +254,10 @@ template <bool CLOSED, class R, int SPL>
 __device__ __forceinline__ void even_x(Row<R, SPL>& w, R s, R d, const XPairs<SPL / 2, CLOSED>& m) {
 #pragma unroll
     for (int p = 0; p < SPL / 2; ++p) {
-        const R a0 = w.re[2 * p], a1 = w.im[2 * p], b0 = w.re[2 * p + 1], b1 = w.im[2 * p + 1];
-        rot_pair(w.re[2 * p], w.im[2 * p], w.re[2 * p + 1], w.im[2 * p + 1], s, d);
-        if constexpr (CLOSED) {
-            keep_old(m.even[p], w.re[2 * p], a0);
-            keep_old(m.even[p], w.im[2 * p], a1);
-            keep_old(m.even[p], w.re[2 * p + 1], b0);
-            keep_old(m.even[p], w.im[2 * p + 1], b1);
-        } else {
-            (void)a0; (void)a1; (void)b0; (void)b1;
-        }
+        bool ok = true;
+        if constexpr (CLOSED) ok = m.even[p];
+        rot_pair(w.re[2 * p], w.im[2 * p], w.re[2 * p + 1], w.im[2 * p + 1],
+                 pair_coef<CLOSED>(ok, s), pair_coef<CLOSED>(ok, d));
     }
 }
 
@@ -268,28 +268,18 @@ __device__ __forceinline__ void odd_x(Row<R, SPL>& w, R s, R d, const XPairs<SPL
     R lr = from_left(w.re[SPL - 1]), li = from_left(w.im[SPL - 1]);
 #pragma unroll
     for (int p = 0; p + 1 < SPL / 2; ++p) {
-        const R a0 = w.re[2 * p + 1], a1 = w.im[2 * p + 1], b0 = w.re[2 * p + 2], b1 = w.im[2 * p + 2];
-        rot_pair(w.re[2 * p + 1], w.im[2 * p + 1], w.re[2 * p + 2], w.im[2 * p + 2], s, d);
-        if constexpr (CLOSED) {
-            keep_old(m.inner[p], w.re[2 * p + 1], a0);
-            keep_old(m.inner[p], w.im[2 * p + 1], a1);
-            keep_old(m.inner[p], w.re[2 * p + 2], b0);
-            keep_old(m.inner[p], w.im[2 * p + 2], b1);
-        } else {
-            (void)a0; (void)a1; (void)b0; (void)b1;
-        }
+        bool ok = true;
+        if constexpr (CLOSED) ok = m.inner[p];
+        rot_pair(w.re[2 * p + 1], w.im[2 * p + 1], w.re[2 * p + 2], w.im[2 * p + 2],
+                 pair_coef<CLOSED>(ok, s), pair_coef<CLOSED>(ok, d));
     }
-    const R e0 = w.re[SPL - 1], e1 = w.im[SPL - 1], f0 = w.re[0], f1 = w.im[0];
-    rot_site(w.re[SPL - 1], w.im[SPL - 1], rr, ri, s, d);
-    rot_site(w.re[0], w.im[0], lr, li, s, d);
+    bool ok_r = true, ok_l = true;
     if constexpr (CLOSED) {
-        keep_old(m.right, w.re[SPL - 1], e0);
-        keep_old(m.right, w.im[SPL - 1], e1);
-        keep_old(m.left, w.re[0], f0);
-        keep_old(m.left, w.im[0], f1);
-    } else {
-        (void)e0; (void)e1; (void)f0; (void)f1;
+        ok_r = m.right;
+        ok_l = m.left;
     }
+    rot_site(w.re[SPL - 1], w.im[SPL - 1], rr, ri, pair_coef<CLOSED>(ok_r, s), pair_coef<CLOSED>(ok_r, d));
+    rot_site(w.re[0], w.im[0], lr, li, pair_coef<CLOSED>(ok_l, s), pair_coef<CLOSED>(ok_l, d));
 }
 
 // y-pair made of row `u` (upper, smaller y) and row `v` (next row).
@@ -362,8 +352,9 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // k+1's even factors and the potential phase on o.  Stage K-1 = S of the
 // last pass applies only the closing odd factors.  With a time-dependent
 // potential (TD) the phase pair holds (theta0, w) per site and stage k forms
-// step k's factor from a.g[k].  Closed meshes skip the y-pairs that cross a
-// wall (`qk` is the pair stage k completes; a wavefront-uniform test).
+// step k's factor from a.g[k].  Closed meshes rotate the y-pairs that cross
+// a wall with zero coefficients (`qk` is the pair stage k completes; a
+// wavefront-uniform test).
 template <int S, int K, bool CLOSED, bool TD, class R, int SPL, class PT, class PhaseFn>
 __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
                                                const MarchArgs<R>& a,
@@ -382,12 +373,15 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
     const bool ey_ok = !CLOSED || (qk >= 0 && 2 * qk + 1 < a.ny);
     odd_x<CLOSED>(o.g, oxs, oxd, xm);
     odd_x<CLOSED>(n.f, oxs, oxd, xm);
-    if (oy_ok) pair_y(o.g, n.f, oys, oyd);
+    // closed meshes: a y-pair reaching outside the mesh rotates with zero
+    // coefficients (a wavefront-uniform choice, no branch)
+    pair_y(o.g, n.f, oy_ok ? oys : R(0), oy_ok ? oyd : R(0));
     if (k < S) {
         const PhasePair<PT, SPL> ph = phase(k);
         even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
         even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
-        if (ey_ok) pair_y(o.f, o.g, a.ehys, a.ehyd);
+        const R eys = ey_ok ? a.ehys : R(0), eyd = ey_ok ? a.ehyd : R(0);
+        pair_y(o.f, o.g, eys, eyd);
         if constexpr (TD) {
             phase_row_td(o.f, ph.f, a.g[k]);
             phase_row_td(o.g, ph.g, a.g[k]);
@@ -395,7 +389,7 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
             phase_row(o.f, ph.f);
             phase_row(o.g, ph.g);
         }
-        if (ey_ok) pair_y(o.f, o.g, a.ehys, a.ehyd);
+        pair_y(o.f, o.g, eys, eyd);
         even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
         even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
     }
@@ -412,7 +406,7 @@ struct WaveRing {
 };
 
 // Site-wise loads and stores for closed meshes (odd sides allowed, so rows
-// need not start on a 16-byte boundary; sites outside the mesh read as 0).
+// need not start on a 16-byte boundary).
 __device__ __forceinline__ void load_site(const void* base, long long off, double& re, double& im) {
     const double2 v = reinterpret_cast<const double2*>(base)[off];
     re = v.x;
@@ -445,8 +439,8 @@ __device__ __forceinline__ PT zero_phase() {
 // segment upwards: odd segments do, so two neighbouring segments cross the
 // rows they both read (each other's warm-up halo) at the same time, start or
 // end, and the second read can hit L2.  CLOSED: hard walls instead of
-// periodic wrap (rows and columns outside the mesh are zeros that no
-// rotation touches).
+// periodic wrap (rows and columns outside the mesh hold values that no
+// rotation carries inside and that are never stored).
 //
 // Register homes: the row pair that enters the pipeline in iteration j lives
 // in home j mod NH until it is stored K iterations later; stage k of
@@ -499,12 +493,24 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         xm.left = in(xu0 - 1) && in(xu0);
         xm.right = in(xu0 + SPL - 1) && in(xu0 + SPL);
     }
+    // Closed meshes: a site outside the mesh loads any site inside (its column
+    // and row clamped to the mesh) instead of a zero, since no rotation lets
+    // its value reach a site inside (x-pairs reaching outside run with zero
+    // coefficients, y-pairs reaching outside are skipped) and it is never
+    // stored; the loads need no condition.
+    int ccol[SPL];
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+        const long long x = xu0 + i;
+        ccol[i] = CLOSED ? (int)(x < 0 ? 0 : (x >= nx ? nx - 1 : x)) : 0;
+    }
+    auto clamp_row = [&](int r) { return r < 0 ? 0 : (r >= ny ? ny - 1 : r); };
 
     // y: output row pairs [q0, q1); input pairs [q0 - K, q1 - 1 + K], visited in
     // increasing order (decreasing when marching up).  `rpsi` and `rph` are the
     // first rows of the next pair whose psi, respectively phase, is loaded,
     // stepped by two rows (periodic wrap; closed meshes leave them unwrapped
-    // and treat rows outside [0, ny) as zeros).
+    // and load rows outside [0, ny) from the nearest row of the mesh).
     const int hp = CLOSED ? (ny + 1) >> 1 : ny >> 1;
     const int q0 = seg * (a.seg_rows >> 1);
     const int q1 = min(q0 + (a.seg_rows >> 1), hp);
@@ -525,13 +531,9 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     };
     auto load_row = [&](int r, Row<R, SPL>& w) {
         if constexpr (CLOSED) {
-            const bool row_ok = r >= 0 && r < ny;
-            const long long off = (long long)r * nx + xu0;
+            const long long off = (long long)clamp_row(r) * nx;
 #pragma unroll
-            for (int i = 0; i < SPL; ++i) {
-                w.re[i] = w.im[i] = R(0);
-                if (row_ok && site_ok[i]) load_site(a.src, off + i, w.re[i], w.im[i]);
-            }
+            for (int i = 0; i < SPL; ++i) load_site(a.src, off + ccol[i], w.re[i], w.im[i]);
         } else {
             const long long off = (long long)r * nx;
 #pragma unroll
@@ -546,10 +548,9 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     auto load_phase_row = [&](int r, PT (&v)[SPL]) {
         const PT* P = reinterpret_cast<const PT*>(a.ptab);
         if constexpr (CLOSED) {
-            const bool row_ok = r >= 0 && r < ny;
-            const long long off = (long long)r * nx + xu0;
+            const long long off = (long long)clamp_row(r) * nx;
 #pragma unroll
-            for (int i = 0; i < SPL; ++i) v[i] = (row_ok && site_ok[i]) ? P[off + i] : zero_phase<PT>();
+            for (int i = 0; i < SPL; ++i) v[i] = P[off + ccol[i]];
         } else {
             const long long off = (long long)r * nx;
 #pragma unroll
@@ -618,9 +619,9 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     // One march iteration with static home indices (u = j mod NH).
     auto iteration = [&](auto U) {
         constexpr int u = decltype(U)::value;
-        // The last iteration loads one pair more than the march uses (a row
-        // of the mesh, or zeros outside a closed mesh): an unconditional load
-        // keeps the homes free of merges.
+        // The last iteration loads one pair more than the march uses (always
+        // rows of the mesh): an unconditional load keeps the homes free of
+        // merges.
         load_psi(home[(u + 1) % NH]);
         load_phase(ph[u % NP]);
         static_for<K>([&](auto KK) {
