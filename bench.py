@@ -530,6 +530,27 @@ def cpu_baseline(p, psi0_host, V_host, sample_steps: int):
                       f"{p.steps} steps, FP64 C oracle (OpenMP over lines), {dt:.1f} s"}
 
 
+def workload_line(res: dict, args, workload: str, mesh, steps: int, dt: float, **extra) -> dict:
+    """The JSON line of a workload measured per dtype (`res`: dtype -> run result):
+    complex64 at the top level when it was measured, the other dtype nested."""
+    head = "c64" if "c64" in res else next(iter(res))
+    r = res[head]
+    line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,
+            "data": "synthetic",
+            "config": {"workload": workload, "mesh": list(mesh), "time_steps_per_solve": steps,
+                       "dt": dt, **extra, **r["schedule"]},
+            "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
+    for d, rr in res.items():
+        if d != head:
+            line["complex128" if d == "c128" else "complex64"] = {
+                "dtype": d, "value": rr["value"], "unit": "site-steps/s",
+                "ms_per_step": rr["ms_per_step"], "config": rr["schedule"],
+                "roofline": rr["roofline"], "norm_drift": rr["norm_drift"]}
+    return line
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -583,15 +604,9 @@ def main() -> int:
         log("generating inputs on the device")
         psi0 = wl.initial_state(p, device="cuda", dtype=torch.complex64)
         V = wl.potential(p, device="cuda")
-        r = run_dtype("c64", p, psi0, V, args)
-        line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
-                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
-                "data": "synthetic",
-                "config": {"workload": "packets_bumps_32768x32768_dt0.05_200steps",
-                           "mesh": [p.nx, p.ny], "time_steps_per_solve": p.steps, "dt": p.dt,
-                           **r["schedule"]},
-                "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
+        res = {"c64": run_dtype("c64", p, psi0, V, args)}
+        line = workload_line(res, args, "packets_bumps_32768x32768_dt0.05_200steps", (p.nx, p.ny),
+                             p.steps, p.dt)
         print(json.dumps(line), flush=True)
         return 0
     if args.workload == "closed4096":
@@ -600,20 +615,8 @@ def main() -> int:
         psi0 = wl.initial_state(p, device="cuda")
         V = wl.potential(p, device="cuda")
         res = {d: run_dtype(d, p, psi0, V, args, bc="closed") for d in args.dtypes.split(",")}
-        r = res["c64"] if "c64" in res else next(iter(res.values()))
-        line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
-                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "c64" if "c64" in res else "c128", "data": "synthetic",
-                "config": {"workload": "packets_bumps_4096x4096_dt0.05_1000steps_closed",
-                           "mesh": [p.nx, p.ny], "time_steps_per_solve": p.steps, "dt": p.dt,
-                           "boundary": "closed", **r["schedule"]},
-                "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
-        if "c128" in res and "c64" in res:
-            rr = res["c128"]
-            line["complex128"] = {"dtype": "c128", "value": rr["value"], "unit": "site-steps/s",
-                                  "ms_per_step": rr["ms_per_step"], "config": rr["schedule"],
-                                  "roofline": rr["roofline"], "norm_drift": rr["norm_drift"]}
+        line = workload_line(res, args, "packets_bumps_4096x4096_dt0.05_1000steps_closed",
+                             (p.nx, p.ny), p.steps, p.dt, boundary="closed")
         print(json.dumps(line), flush=True)
         return 0
     if args.workload == "order4_4096":
@@ -623,20 +626,9 @@ def main() -> int:
         psi0 = wl.initial_state(p, device="cuda")
         V = wl.potential(p, device="cuda")
         res = {d: run_dtype(d, p, psi0, V, args, order=4) for d in args.dtypes.split(",")}
-        r = res["c64"] if "c64" in res else next(iter(res.values()))
-        line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
-                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "c64" if "c64" in res else "c128", "data": "synthetic",
-                "config": {"workload": "packets_bumps_4096x4096_dt0.05_200steps_order4",
-                           "mesh": [p.nx, p.ny], "time_steps_per_solve": p.steps, "dt": p.dt,
-                           "order": 4, "second_order_sub_steps_per_step": 5, **r["schedule"]},
-                "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
-        if "c128" in res and "c64" in res:
-            rr = res["c128"]
-            line["complex128"] = {"dtype": "c128", "value": rr["value"], "unit": "site-steps/s",
-                                  "ms_per_step": rr["ms_per_step"], "config": rr["schedule"],
-                                  "roofline": rr["roofline"], "norm_drift": rr["norm_drift"]}
+        line = workload_line(res, args, "packets_bumps_4096x4096_dt0.05_200steps_order4",
+                             (p.nx, p.ny), p.steps, p.dt, order=4,
+                             second_order_sub_steps_per_step=5)
         print(json.dumps(line), flush=True)
         return 0
     if args.workload == "mesh3d512":
@@ -645,20 +637,8 @@ def main() -> int:
         psi0 = wl.state3(p, device="cuda")
         V = wl.potential3(p, device="cuda")
         res = {d: run_3d(d, p, psi0, V, args) for d in args.dtypes.split(",")}
-        r = res["c64"] if "c64" in res else next(iter(res.values()))
-        line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
-                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "c64" if "c64" in res else "c128", "data": "synthetic",
-                "config": {"workload": "packet_well_512x512x512_dt0.05_100steps",
-                           "mesh": [p.nx, p.ny, p.nz], "time_steps_per_solve": p.steps,
-                           "dt": p.dt, **r["schedule"]},
-                "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
-        if "c128" in res and "c64" in res:
-            rr = res["c128"]
-            line["complex128"] = {"dtype": "c128", "value": rr["value"], "unit": "site-steps/s",
-                                  "ms_per_step": rr["ms_per_step"], "config": rr["schedule"],
-                                  "roofline": rr["roofline"], "norm_drift": rr["norm_drift"]}
+        line = workload_line(res, args, "packet_well_512x512x512_dt0.05_100steps",
+                             (p.nx, p.ny, p.nz), p.steps, p.dt)
         print(json.dumps(line), flush=True)
         return 0
     if args.workload == "td4096":
@@ -669,20 +649,10 @@ def main() -> int:
         W = wl.standing_wave(p, device="cuda")
         f = wl.drive(p.dt, p.steps)
         res = {d: run_td(d, p, psi0, V0, W, f, args) for d in args.dtypes.split(",")}
-        r = res["c64"] if "c64" in res else next(iter(res.values()))
-        line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
-                "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "c64" if "c64" in res else "c128", "data": "synthetic",
-                "config": {"workload": "packets_bumps_4096x4096_dt0.05_1000steps_shaken_standing_wave",
-                           "mesh": [p.nx, p.ny], "time_steps_per_solve": p.steps, "dt": p.dt,
-                           "drive": "V0 + 0.2 sin(0.5 t) cos(8 pi i / 4096) at column i", **r["schedule"]},
-                "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
-        if "c128" in res and "c64" in res:
-            rr = res["c128"]
-            line["complex128"] = {"dtype": "c128", "value": rr["value"], "unit": "site-steps/s",
-                                  "ms_per_step": rr["ms_per_step"], "config": rr["schedule"],
-                                  "roofline": rr["roofline"], "norm_drift": rr["norm_drift"]}
+        line = workload_line(res, args,
+                             "packets_bumps_4096x4096_dt0.05_1000steps_shaken_standing_wave",
+                             (p.nx, p.ny), p.steps, p.dt,
+                             drive="V0 + 0.2 sin(0.5 t) cos(8 pi i / 4096) at column i")
         print(json.dumps(line), flush=True)
         return 0
     p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 1000, "c64", name="packets_bumps_4096")
