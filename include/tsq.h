@@ -173,7 +173,7 @@ int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws
  * (Sec. 2, footnote to Eq. "evolution", citing Poulin et al.): here step n,
  * from t_n to t_n + dt, is U2(dt) with the potential frozen at the step's
  * midpoint, V0 + f_n W with f_n = f(t_n + dt/2), which keeps the product second
- * order for smooth f.  Periodic order-2 plans of 2D meshes only; every step's phase factor
+ * order for smooth f.  Order-2 plans of 2D meshes (periodic or closed); every step's phase factor
  * exp(-i dt (V0 + f_n W + eps0) / hbar) is formed in FP64 inside the march, so
  * up to 4 steps fuse per pass (a plan scheduled deeper runs 4). */
 
@@ -181,7 +181,7 @@ int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws
  * each) in `ws`: per site dt (V0 + eps0) / hbar and dt W / hbar (16 bytes, the
  * place of the phase table).  Records `ws` for tsq_evolve_td; a later
  * tsq_set_potential makes the workspace time-independent again.
- * Errors: TSQ_ERR_ARG (null), TSQ_ERR_UNSUPPORTED (order 4, closed or 3D mesh),
+ * Errors: TSQ_ERR_ARG (null), TSQ_ERR_UNSUPPORTED (order 4 or 3D mesh),
  * TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
 int tsq_set_potential_td(tsq_plan* plan, const double* V0_dev, const double* W_dev, void* ws,
                          size_t ws_bytes, void* stream);

@@ -705,9 +705,8 @@ int tsq_set_potential_td(tsq_plan* plan, const double* V0, const double* W, void
     if (!plan || !V0 || !W) return fail(TSQ_ERR_ARG, "null plan or potential");
     if (plan->p.order != 2)
         return fail(TSQ_ERR_UNSUPPORTED, "time-dependent potentials run with order-2 plans only");
-    if (plan->p.bc != TSQ_BC_PERIODIC || plan->three_d)
-        return fail(TSQ_ERR_UNSUPPORTED,
-                    "time-dependent potentials run on periodic 2D meshes only");
+    if (plan->three_d)
+        return fail(TSQ_ERR_UNSUPPORTED, "time-dependent potentials run on 2D meshes only");
     int rc = check_ws(plan, ws, ws_bytes);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);

@@ -19,13 +19,15 @@ const void* march_ptr_c128_closed(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c64_closed(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c128_td(int steps, bool last, int ppl, bool lds);
 const void* march_ptr_c64_td(int steps, bool last, int ppl, bool lds);
+const void* march_ptr_c128_closedtd(int steps, bool last, int ppl, bool lds);
+const void* march_ptr_c64_closedtd(int steps, bool last, int ppl, bool lds);
 
 namespace {
 
 struct C128 {};
 struct C64 {};
 
-enum class Variant { Single, Batch, Closed, TimeDep, None };
+enum class Variant { Single, Batch, Closed, TimeDep, ClosedTimeDep };
 
 const void* march_kernel_ptr(int dtype, int steps, bool last, int ppl, bool lds, Variant v) {
     const bool d = dtype == 1;
@@ -38,15 +40,16 @@ const void* march_kernel_ptr(int dtype, int steps, bool last, int ppl, bool lds,
             return d ? march_ptr_c128_closed(steps, last, ppl, lds) : march_ptr_c64_closed(steps, last, ppl, lds);
         case Variant::TimeDep:
             return d ? march_ptr_c128_td(steps, last, ppl, lds) : march_ptr_c64_td(steps, last, ppl, lds);
-        case Variant::None:
-            break;
+        case Variant::ClosedTimeDep:
+            return d ? march_ptr_c128_closedtd(steps, last, ppl, lds)
+                     : march_ptr_c64_closedtd(steps, last, ppl, lds);
     }
     return nullptr;
 }
 
 Variant variant_of(bool batch, bool closed, bool td) {
     if (batch) return Variant::Batch;
-    if (td) return closed ? Variant::None : Variant::TimeDep;  // no closed time-dependent march
+    if (td) return closed ? Variant::ClosedTimeDep : Variant::TimeDep;
     return closed ? Variant::Closed : Variant::Single;
 }
 

@@ -711,9 +711,9 @@ march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
 // 1 pair per lane, 1..kMaxRegSteps2 with 2, periodic LDS ring for
 // 1..kMaxSteps (1 pair per lane), single and batched; closed meshes: both
 // rings with 1 pair per lane, single only; time-dependent potentials
-// (periodic): both rings, 1 pair per lane, at most kMaxTdSteps steps per
-// pass, single only.
-enum class Variant { Single, Batch, Closed, TimeDep };
+// (periodic or closed): both rings, 1 pair per lane, at most kMaxTdSteps
+// steps per pass, single only.
+enum class Variant { Single, Batch, Closed, TimeDep, ClosedTimeDep };
 
 template <class T, int S, bool LAST, int PPL, bool LDS, Variant V>
 const void* kernel_ptr() {
@@ -725,8 +725,10 @@ const void* kernel_ptr() {
         return nullptr;
     else if constexpr (V == Variant::Closed)
         return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, true, false>);
-    else
+    else if constexpr (V == Variant::TimeDep)
         return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, false, true>);
+    else
+        return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, true, true>);
 }
 
 template <class T, Variant V, bool LAST, int PPL, bool LDS, int... Ss>
@@ -742,15 +744,15 @@ const void* pick_variant(int steps, int ppl, bool lds) {
         if (ppl != 1) return nullptr;
         // the time-dependent march evaluates a sine and cosine per site and
         // step; beyond 4 steps per pass its loop outgrows the instruction cache
-        if constexpr (V == Variant::TimeDep)
+        if constexpr (V == Variant::TimeDep || V == Variant::ClosedTimeDep)
             return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxTdSteps>());
         return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxSteps>());
     }
     if (ppl == 2) {
-        if constexpr (V == Variant::Closed || V == Variant::TimeDep) return nullptr;
+        if constexpr (V != Variant::Single && V != Variant::Batch) return nullptr;
         return pick_steps<T, V, LAST, 2, false>(steps, std::make_integer_sequence<int, kMaxRegSteps2>());
     }
-    if constexpr (V == Variant::TimeDep)
+    if constexpr (V == Variant::TimeDep || V == Variant::ClosedTimeDep)
         return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxTdSteps>());
     return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
 }

@@ -129,12 +129,23 @@ def test_calls_reject_null_and_out_of_order_before_any_launch():
         tsq.tsq_plan_destroy(h)
 
 
-@pytest.mark.parametrize("kw", [dict(order=4), dict(bc=1, nx=63)])
-def test_time_dependent_potential_needs_periodic_order2(kw):
+@pytest.mark.parametrize("kw", [dict(order=4), dict(nz=8)])
+def test_time_dependent_potential_needs_order2_2d(kw):
     lib = tsq.load_library()
     h = tsq.tsq_plan_create(problem(**kw))
     try:
         assert lib.tsq_set_potential_td(h, 16, 16, 256, 1 << 30, None) == -7
+    finally:
+        tsq.tsq_plan_destroy(h)
+
+
+def test_time_dependent_potential_accepts_closed_meshes():
+    """Closed 2D meshes take time-dependent potentials: validation passes the boundary
+    and stops only at the workspace (too small here)."""
+    lib = tsq.load_library()
+    h = tsq.tsq_plan_create(problem(bc=1, nx=63))
+    try:
+        assert lib.tsq_set_potential_td(h, 16, 16, 256, 16, None) == -4
     finally:
         tsq.tsq_plan_destroy(h)
 

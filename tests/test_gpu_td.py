@@ -56,6 +56,60 @@ def test_td_ragged_meshes(shape, S, dtype):
             assert err <= TOL[dtype], (shape, S, store, steps, err)
 
 
+CLOSED_SHAPES = [(2, 2), (3, 5), (131, 67), (257, 301)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("S", [1, 3, 4])
+@pytest.mark.parametrize("shape", CLOSED_SHAPES)
+def test_td_closed_meshes(shape, S, dtype):
+    """The time-dependent potential between hard walls (odd sides allowed) against the
+    oracle's closed mesh, both phase rings."""
+    nx, ny = shape
+    psi0 = wl.random_state(nx, ny, 70 + nx)
+    V0 = wl.random_potential(nx, ny, 71 + ny, scale=0.5)
+    W = wl.random_potential(nx, ny, 72 + nx, scale=0.7)
+    for steps in (1, 2 * S + 1):
+        f = np.random.default_rng(90 + steps).uniform(-1.5, 1.5, steps)
+        want = oracle.evolve_td(as_input(psi0, dtype), V0, W, f, 0.11, bc="closed", **ANISO)
+        for store in (1, 2):
+            got = gpu_evolve_td(psi0, V0, W, f, 0.11, dtype, steps_per_pass=S, segment_rows=16,
+                                phase_store=store, bc="closed", **ANISO)
+            err = rel_l2(got, want)
+            assert err <= TOL[dtype], (shape, S, store, steps, err)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_closed_schedule_does_not_change_a_bit(dtype):
+    nx, ny = 131, 67
+    psi0 = wl.random_state(nx, ny, 80)
+    V0 = wl.random_potential(nx, ny, 81)
+    W = wl.random_potential(nx, ny, 82)
+    f = np.random.default_rng(83).uniform(-1, 1, 9)
+    ref = gpu_evolve_td(psi0, V0, W, f, 0.09, dtype, steps_per_pass=1, segment_rows=2,
+                        phase_store=1, bc="closed")
+    for S in (2, 4, 8):
+        for seg in (2, 10, 0):
+            for store in ((1, 2) if S <= 6 else (2,)):
+                got = gpu_evolve_td(psi0, V0, W, f, 0.09, dtype, steps_per_pass=S,
+                                    segment_rows=seg, phase_store=store, bc="closed")
+                assert np.array_equal(got, ref), (S, seg, store)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_closed_constant_modulation_equals_static_potential(dtype):
+    nx, ny = 129, 95
+    psi0 = wl.random_state(nx, ny, 84)
+    V0 = wl.random_potential(nx, ny, 85, scale=3.0)
+    W = wl.random_potential(nx, ny, 86, scale=2.0)
+    c = -0.41
+    got = gpu_evolve_td(psi0, V0, W, np.full(30, c), 0.2, dtype, bc="closed", **ANISO)
+    want = gpu_evolve(psi0, V0 + c * W, 0.2, 30, dtype, bc="closed", **ANISO)
+    err = rel_l2(got, want)
+    log(f"  td closed constant f vs static {dtype}: {err:.3e}")
+    assert err <= (1e-13 if dtype == "c128" else 2e-6)
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_td_schedule_and_call_split_do_not_change_a_bit(dtype):
     """Every schedule gives the same bits (a schedule deeper than the
