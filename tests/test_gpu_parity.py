@@ -212,6 +212,20 @@ def test_fourth_order_matches_oracle(dtype, S):
         assert rel_l2(got, want) <= TOL[dtype], (S, steps)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("S", [1, 4, 6])
+def test_fourth_order_closed_matches_oracle(dtype, S):
+    """The fourth-order product between hard walls, odd sides, against the oracle."""
+    nx, ny = 131, 67
+    psi0 = wl.random_state(nx, ny, 43)
+    V = wl.random_potential(nx, ny, 44, scale=0.5)
+    for steps in (1, 3):
+        want = oracle_evolve(psi0, V, 0.11, steps, dtype, order=4, bc="closed", **ANISO)
+        got = gpu_evolve(psi0, V, 0.11, steps, dtype, steps_per_pass=S, order=4, bc="closed",
+                         **ANISO)
+        assert rel_l2(got, want) <= TOL[dtype], (S, steps)
+
+
 CLOSED_SHAPES = [(2, 2), (3, 5), (7, 4), (131, 67), (66, 301)]
 
 
