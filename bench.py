@@ -168,7 +168,7 @@ def run_dtype(dtype: str, p, psi0, V, args, order: int = 2, bc: str = "periodic"
     }
 
 
-def run_td(dtype: str, p, psi0, V0, W, f, args):
+def run_td(dtype: str, p, psi0, V0, W, f, args, bc: str = "periodic"):
     """One solve under the time-dependent potential V0 + f(t) W: table setup,
     len(f) fused steps (the phase formed in FP64 in the march), FP64 observables
     at the final time."""
@@ -177,7 +177,7 @@ def run_td(dtype: str, p, psi0, V0, W, f, args):
 
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
     psi = psi0.to(tdt).contiguous()
-    plan = tsq.Plan(p.nx, p.ny, p.dt, dtype, device=psi.device)
+    plan = tsq.Plan(p.nx, p.ny, p.dt, dtype, bc=bc, device=psi.device)
     plan.set_potential_td(V0, W)
     if args.schedule:
         plan.set_schedule(*[int(v) for v in args.schedule.split(",")])
@@ -570,14 +570,14 @@ def main() -> int:
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--workload", default="mesh4096",
                     choices=["mesh4096", "mesh32768", "batch512", "served", "td4096", "mesh3d512",
-                             "order4_4096", "closed4096"],
+                             "order4_4096", "closed4096", "td_closed4096"],
                     help="mesh4096: the benchmark line; mesh32768: 32768^2 complex64, 200 "
                          "steps; batch512: 512 uneven complex64 problems, 500 steps; "
                          "served: Poisson request stream into the batching server; td4096: "
                          "the 4096^2 workload under a time-dependent potential; mesh3d512: "
                          "512^3 packet in a harmonic well, 100 steps; order4_4096: the 4096^2 "
                          "workload under the fourth-order product, 200 steps; closed4096: the 4096^2 "
-                         "workload between hard walls")
+                         "workload between hard walls; td_closed4096: td4096 between hard walls")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--fifo-seconds", type=float, default=10.0)
     ap.add_argument("--block-steps", type=int, default=20)
@@ -641,17 +641,18 @@ def main() -> int:
                              (p.nx, p.ny, p.nz), p.steps, p.dt)
         print(json.dumps(line), flush=True)
         return 0
-    if args.workload == "td4096":
+    if args.workload in ("td4096", "td_closed4096"):
         p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 1000, "c64", name="packets_bumps_4096")
         log("generating inputs on the device")
         psi0 = wl.initial_state(p, device="cuda")
         V0 = wl.potential(p, device="cuda")
         W = wl.standing_wave(p, device="cuda")
         f = wl.drive(p.dt, p.steps)
-        res = {d: run_td(d, p, psi0, V0, W, f, args) for d in args.dtypes.split(",")}
-        line = workload_line(res, args,
-                             "packets_bumps_4096x4096_dt0.05_1000steps_shaken_standing_wave",
-                             (p.nx, p.ny), p.steps, p.dt,
+        bc = "closed" if args.workload == "td_closed4096" else "periodic"
+        res = {d: run_td(d, p, psi0, V0, W, f, args, bc=bc) for d in args.dtypes.split(",")}
+        name = "packets_bumps_4096x4096_dt0.05_1000steps_shaken_standing_wave"
+        line = workload_line(res, args, name + ("_closed" if bc == "closed" else ""),
+                             (p.nx, p.ny), p.steps, p.dt, boundary=bc,
                              drive="V0 + 0.2 sin(0.5 t) cos(8 pi i / 4096) at column i")
         print(json.dumps(line), flush=True)
         return 0
