@@ -70,7 +70,7 @@ typedef enum {
     TSQ_ERR_WORKSPACE = -4,   /* workspace too small or misaligned */
     TSQ_ERR_DEVICE = -5,      /* a HIP call failed; see tsq_last_error() */
     TSQ_ERR_STATE = -6,       /* call out of order (e.g. evolve before set_potential, other ws) */
-    TSQ_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+    TSQ_ERR_UNSUPPORTED = -7  /* valid request the library does not implement */
 } tsq_status;
 
 typedef enum { TSQ_C64 = 0, TSQ_C128 = 1 } tsq_dtype;
