@@ -467,7 +467,8 @@ def run_batch(args) -> dict:
         "data": "synthetic",
         "config": {"workload": "batch512_c64_500steps", "problems": len(probs), "sites": sites,
                    "site_steps_per_call": site_steps, "steps_per_pass": sched[0],
-                   "phase_store": "lds", "launches_per_call": launches, "tiles_per_call": tiles,
+                   "phase_store": "registers" if sched[3] == 1 else "lds",
+                   "launches_per_call": launches, "tiles_per_call": tiles,
                    "hip_graph": True},
         "sequential": {"value": site_steps / t_seq, "ms_per_call": t_seq * 1e3},
         "speedup_vs_sequential": t_seq / t_batch,
