@@ -62,3 +62,35 @@ def crop_periodic(a: np.ndarray, y0: int, x0: int, h: int, w: int) -> np.ndarray
     ys = np.arange(y0, y0 + h) % a.shape[0]
     xs = np.arange(x0, x0 + w) % a.shape[1]
     return a[np.ix_(ys, xs)]
+
+
+def light_cone_windows(got: np.ndarray, fields, run_oracle, windows, h: int, w: int, m: int,
+                       bc: str):
+    """Relative L2 of `h` x `w` windows of a full-mesh result `got` against oracle
+    runs on each window plus a margin of `m` sites (at least the light cone of the
+    run).  `fields` are the full-mesh input arrays the oracle needs (state first);
+    `run_oracle(*crops, bc=...)` evolves the cropped arrays.  Periodic meshes crop
+    with wrap-around and run the crop periodic; closed meshes clip the crop at the
+    mesh walls and run it closed, so true walls stay walls and every cut edge lies
+    at least `m` sites from the window.  Pairs are fixed by site parity, so a
+    crop must start on an even site: windows start on even sites and the margin is
+    rounded up to even."""
+    ny, nx = got.shape
+    m += m & 1
+    errs = []
+    for y0, x0 in windows:
+        if (y0 | x0) & 1:
+            raise ValueError(f"window ({y0}, {x0}) does not start on an even site")
+        if bc == "periodic":
+            crops = [crop_periodic(f, y0 - m, x0 - m, h + 2 * m, w + 2 * m) for f in fields]
+            oy, ox = m, m
+        else:
+            ya, yb = max(0, y0 - m), min(ny, y0 + h + m)
+            xa, xb = max(0, x0 - m), min(nx, x0 + w + m)
+            crops = [np.ascontiguousarray(f[ya:yb, xa:xb]) for f in fields]
+            oy, ox = y0 - ya, x0 - xa
+        want = run_oracle(*crops, bc=bc)[oy:oy + h, ox:ox + w]
+        g = crop_periodic(got, y0, x0, h, w)
+        if np.linalg.norm(want) > 0:
+            errs.append(rel_l2(g, want))
+    return errs

@@ -11,8 +11,8 @@ import oracle
 from oracle import closed_form as cf
 import paper_1208_2407_amd as tsq
 from paper_1208_2407_amd import workloads as wl
-from tests.gpu_helpers import (TOL, as_input, crop_periodic, gpu_evolve, log, oracle_evolve,
-                               rel_l2)
+from tests.gpu_helpers import (TOL, as_input, gpu_evolve, light_cone_windows, log,
+                               oracle_evolve, rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -143,30 +143,22 @@ def test_mesh4096_sampled_windows(dtype):
     checked against oracle runs on the window plus its light cone (2N+1 sites per side,
     rounded up to an even margin)."""
     p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 50, dtype)
-    psi0 = wl.initial_state(p).numpy()
+    # the packets plus seeded noise over the whole mesh: every window holds a state
+    psi0 = wl.initial_state(p).numpy() + 0.5 * wl.random_state(4096, 4096, 62)
     V = wl.potential(p).numpy()
     runs = [gpu_evolve(psi0, V, p.dt, p.steps, dtype, steps_per_pass=S, phase_store=1)
             for S in (5, 6)]
     assert np.array_equal(runs[0], runs[1])
-    got = runs[0]
-    m = 2 * p.steps + 2
     h = w = 256
-    ref_in = as_input(psi0, dtype)
     # windows centred on the packets and one across the periodic corner
-    centres = [(int(q.y0 + 2048) // 2 * 2, int(q.x0 + 2048) // 2 * 2) for q in p.packets]
-    centres.append((0, 0))
-    errs = []
-    for (yc, xc) in centres:
-        y0, x0 = yc - h // 2, xc - w // 2
-        sub = crop_periodic(ref_in, y0 - m, x0 - m, h + 2 * m, w + 2 * m)
-        subV = crop_periodic(V, y0 - m, x0 - m, h + 2 * m, w + 2 * m)
-        want = oracle.evolve(sub, subV, p.dt, p.steps)[m:m + h, m:m + w]
-        g = crop_periodic(got, y0, x0, h, w)
-        if np.linalg.norm(want) == 0:
-            continue
-        errs.append(rel_l2(g, want))
-    log(f"  mesh4096 windows {dtype}: max rel L2 {max(errs):.3e}")
-    assert max(errs) <= TOL[dtype]
+    wins = [((int(q.y0 + 2048) - h // 2) // 2 * 2, (int(q.x0 + 2048) - w // 2) // 2 * 2)
+            for q in p.packets]
+    wins.append((-h // 2, -w // 2))
+    errs = light_cone_windows(runs[0], [as_input(psi0, dtype), V],
+                              lambda s, v, bc: oracle.evolve(s, v, p.dt, p.steps, bc=bc),
+                              wins, h, w, 2 * p.steps + 2, "periodic")
+    log(f"  mesh4096 windows {dtype}: max rel L2 {max(errs):.3e} over {len(errs)}")
+    assert len(errs) == len(wins) and max(errs) <= TOL[dtype]
 
 
 @pytest.mark.slow
@@ -270,3 +262,29 @@ def test_closed_observables_match_oracle(dtype):
     n, e = plan.observables(psi, torch.from_numpy(V).cuda())
     n0, e0 = oracle.observables(psi0, V, bc="closed", **ANISO)
     assert abs(n - n0) <= 1e-13 * n0 and abs(e - e0) <= 1e-12 * max(1.0, abs(e0))
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_closed4096_sampled_windows(dtype):
+    """The 4096^2 packets-and-bumps workload between hard walls at full size in the
+    schedules its tuner picks among (5 and 6 steps per pass, both phase rings; all
+    bitwise equal), 50 steps; 256^2 windows on the packets, at a corner and along an
+    edge against oracle runs on closed crops clipped at the walls."""
+    p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 50, dtype)
+    # the packets plus seeded noise over the whole mesh: every window, the walls'
+    # included, holds a state
+    psi0 = wl.initial_state(p).numpy() + 0.5 * wl.random_state(4096, 4096, 61)
+    V = wl.potential(p).numpy()
+    runs = [gpu_evolve(psi0, V, p.dt, p.steps, dtype, steps_per_pass=S, phase_store=st,
+                       bc="closed") for S in (5, 6) for st in (1, 2)]
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    h = w = 256
+    wins = [((int(q.y0 + 2048) - h // 2) // 2 * 2, (int(q.x0 + 2048) - w // 2) // 2 * 2)
+            for q in p.packets]
+    wins += [(0, 0), (4096 - h, 4096 - w), (2048, 0), (0, 3000)]
+    errs = light_cone_windows(runs[0], [as_input(psi0, dtype), V],
+                              lambda s, v, bc: oracle.evolve(s, v, p.dt, p.steps, bc=bc),
+                              wins, h, w, 2 * p.steps + 2, "closed")
+    log(f"  closed4096 windows {dtype}: max rel L2 {max(errs):.3e} over {len(errs)}")
+    assert len(errs) == len(wins) and max(errs) <= TOL[dtype]

@@ -9,7 +9,7 @@ import torch
 import oracle
 import paper_1208_2407_amd as tsq
 from paper_1208_2407_amd import workloads as wl
-from tests.gpu_helpers import TOL, TORCH_DT, as_input, gpu_evolve, log, rel_l2
+from tests.gpu_helpers import TOL, TORCH_DT, as_input, gpu_evolve, light_cone_windows, log, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -223,3 +223,33 @@ def test_td_state_errors():
     assert ei.value.status == -1
     plan.set_schedule(8, 0, 1, 2)
     assert plan.passes(8) == (2, False)   # runs 4 steps per pass
+
+
+@pytest.mark.parametrize("bc", ["periodic", "closed"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td4096_sampled_windows(dtype, bc):
+    """The 4096^2 driven workload (packets and bumps under the shaken standing wave)
+    at full size in the schedules its tuner picks among (3 and 4 steps per pass, both
+    phase rings; all bitwise equal), 50 steps; 256^2 windows on the packets and at the
+    mesh corner (and, between walls, along an edge) against oracle runs on the window
+    plus its light cone."""
+    p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 50, dtype)
+    # the packets plus seeded noise over the whole mesh: every window, the walls'
+    # included, holds a state
+    psi0 = wl.initial_state(p).numpy() + 0.5 * wl.random_state(4096, 4096, 61)
+    V0 = wl.potential(p).numpy()
+    W = wl.standing_wave(p).numpy()
+    f = wl.drive(p.dt, p.steps)
+    runs = [gpu_evolve_td(psi0, V0, W, f, p.dt, dtype, steps_per_pass=S, phase_store=st, bc=bc)
+            for S in (3, 4) for st in (1, 2)]
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    h = w = 256
+    wins = [((int(q.y0 + 2048) - h // 2) // 2 * 2, (int(q.x0 + 2048) - w // 2) // 2 * 2)
+            for q in p.packets]
+    wins += [(0, 0), (4096 - h // 2, 4096 - w // 2)] if bc == "periodic" else [(0, 0), (2048, 4096 - w)]
+    errs = light_cone_windows(runs[0], [as_input(psi0, dtype), V0, W],
+                              lambda s, v, ww, bc: oracle.evolve_td(s, v, ww, f, p.dt, bc=bc),
+                              wins, h, w, 2 * p.steps + 2, bc)
+    log(f"  td4096 {bc} windows {dtype}: max rel L2 {max(errs):.3e} over {len(errs)}")
+    assert len(errs) == len(wins) and max(errs) <= TOL[dtype]

@@ -478,3 +478,35 @@ def test_3d_rejects_bad_arguments():
         oracle.evolve3(psi, V, 0.1, 1)          # odd side under periodic boundaries
     with pytest.raises(ValueError):
         oracle.evolve3(psi, V[:, :, :2], 0.1, 1, bc="closed")
+
+
+@pytest.mark.parametrize("bc", ["periodic", "closed"])
+def test_light_cone_windows_reproduce_the_full_run(bc):
+    """The window check the full-size GPU tests use: oracle runs on windows plus a
+    light-cone margin (wrapped crops on a periodic mesh, crops clipped at the walls
+    on a closed one) reproduce the oracle's full-mesh run inside every window,
+    static and time-dependent."""
+    from tests.gpu_helpers import light_cone_windows
+    ny, nx, N = 150, 170, 9
+    psi = wl.random_state(nx, ny, 90)
+    V = wl.random_potential(nx, ny, 91)
+    W = wl.random_potential(nx, ny, 92)
+    f = np.random.default_rng(93).uniform(-1, 1, N)
+    wins = [(0, 0), (60, 70), (ny - 20, nx - 30), (ny - 10, 6)] if bc == "periodic" else \
+        [(0, 0), (60, 70), (ny - 24, nx - 32), (100, 0)]
+    full = oracle.evolve(psi, V, 0.1, N, bc=bc, **ANISO)
+    errs = light_cone_windows(full, [psi, V], lambda s, v, bc: oracle.evolve(s, v, 0.1, N, bc=bc, **ANISO),
+                              wins, 24, 32, 2 * N + 2, bc)
+    assert len(errs) == 4 and max(errs) < 1e-14, errs
+    full = oracle.evolve_td(psi, V, W, f, 0.1, bc=bc)
+    errs = light_cone_windows(full, [psi, V, W],
+                              lambda s, v, w, bc: oracle.evolve_td(s, v, w, f, 0.1, bc=bc),
+                              wins, 24, 32, 2 * N + 2, bc)
+    assert len(errs) == 4 and max(errs) < 1e-14, errs
+    # a margin inside the light cone is caught
+    errs = light_cone_windows(full, [psi, V, W],
+                              lambda s, v, w, bc: oracle.evolve_td(s, v, w, f, 0.1, bc=bc),
+                              wins[1:2], 24, 32, N // 2, bc)
+    assert errs[0] > 1e-6
+    with pytest.raises(ValueError):
+        light_cone_windows(full, [psi, V, W], None, [(61, 70)], 24, 32, 2 * N + 2, bc)
