@@ -288,3 +288,28 @@ def test_closed4096_sampled_windows(dtype):
                               wins, h, w, 2 * p.steps + 2, "closed")
     log(f"  closed4096 windows {dtype}: max rel L2 {max(errs):.3e} over {len(errs)}")
     assert len(errs) == len(wins) and max(errs) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_order4_4096_sampled_windows(dtype):
+    """The fourth-order product on the full 4096^2 workload in the schedules its tuner
+    picks among (4 steps per pass, both phase rings, and 3 steps per pass; all bitwise
+    equal), 10 fourth-order steps (50 sub-steps, light cone 2 x 50 + 1); 256^2 windows
+    on the packets and across the periodic corner against the oracle's fourth order."""
+    N = 10
+    p = wl.packets_and_bumps(4096, 4096, 2, 0.05, N, dtype)
+    psi0 = wl.initial_state(p).numpy() + 0.5 * wl.random_state(4096, 4096, 63)
+    V = wl.potential(p).numpy()
+    runs = [gpu_evolve(psi0, V, p.dt, N, dtype, steps_per_pass=S, phase_store=st, order=4)
+            for S, st in ((4, 1), (4, 2), (3, 1))]
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    h = w = 256
+    wins = [((int(q.y0 + 2048) - h // 2) // 2 * 2, (int(q.x0 + 2048) - w // 2) // 2 * 2)
+            for q in p.packets]
+    wins.append((-h // 2, -w // 2))
+    errs = light_cone_windows(runs[0], [as_input(psi0, dtype), V],
+                              lambda s, v, bc: oracle.evolve(s, v, p.dt, N, bc=bc, order=4),
+                              wins, h, w, 2 * 5 * N + 2, "periodic")
+    log(f"  order4 4096 windows {dtype}: max rel L2 {max(errs):.3e} over {len(errs)}")
+    assert len(errs) == len(wins) and max(errs) <= TOL[dtype]
