@@ -34,6 +34,9 @@ def log(msg: str) -> None:
 # (the 3D and time-dependent paths live in files of their own).
 KERNEL_SOURCES = ("tsq_march.hpp", "tsq_internal.h", "tsq_kernels.hip", "march_c64_single.hip",
                   "march_c128_single.hip")
+# the 3D march includes the 2D march templates
+KERNEL3_SOURCES = ("tsq_march.hpp", "tsq_internal.h", "tsq_march3.hpp", "tsq_internal3.h",
+                   "tsq_kernels3.hip", "march3_c64.hip", "march3_c128.hip")
 
 
 def code_text(src: str) -> str:
@@ -63,29 +66,32 @@ def code_text(src: str) -> str:
     return " ".join("".join(out).split())
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=KERNEL_SOURCES) -> str:
     """sha256[:16] of the code (comments and layout removed) of the sources of the
-    benchmarked march kernels."""
+    benchmarked march kernels (the 2D march by default)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1208_2407_amd", "csrc")
-    for name in KERNEL_SOURCES:
+    for name in sources:
         h.update(name.encode())
         with open(os.path.join(csrc, name), encoding="utf-8") as fh:
             h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
-def committed_traffic(dtype: str, schedule, nx: int, ny: int) -> float | None:
+def committed_traffic(dtype: str, schedule, nx: int, ny: int, nz: int = 0) -> float | None:
     """HBM bytes per launch from the committed rocprofv3 counter runs (keyed by
-    kernel code hash, mesh "NXxNY", dtype and schedule "S,seg,ppl,store"), if they
-    were taken on this exact kernel code, mesh and schedule; else None."""
+    kernel code hash, mesh "NXxNY" or "NXxNYxNZ", dtype and schedule "S,seg,ppl,store",
+    or "1" for the one-step 3D pass), if they were taken on this exact kernel code,
+    mesh and schedule; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             db = json.load(f)
     except (OSError, ValueError):
         return None
-    e = (db.get(kernel_hash(), {}).get(f"{nx}x{ny}", {}).get(dtype, {})
+    code = kernel_hash(KERNEL3_SOURCES) if nz else kernel_hash()
+    mesh = f"{nx}x{ny}x{nz}" if nz else f"{nx}x{ny}"
+    e = (db.get(code, {}).get(mesh, {}).get(dtype, {})
          .get(",".join(str(int(v)) for v in schedule)))
     if not e:
         return None
@@ -281,13 +287,17 @@ def run_3d(dtype: str, p, psi0, V, args):
     alg_bytes = p.sites * (2 * elem + 16)
     launch_s = evolve_ms * 1e-3 / (args.steps * passes)
     achieved = alg_bytes / launch_s / 1e9
+    traffic = committed_traffic(dtype, (1,), p.nx, p.ny, p.nz)
     log(f"3d {dtype}: {wall / args.steps * 1e3:.2f} ms/solve, {site_steps / wall:.4e} site-steps/s, "
         f"pass {launch_s * 1e6:.1f} us, {achieved:.0f} GB/s algorithmic, norm {norm:.15f}")
     return {
         "value": site_steps / wall, "ms_per_step": wall / args.steps * 1e3,
         "schedule": {"steps_per_pass": 1, "passes_per_solve": passes, "copy_back": copy_back},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_GBps": round(traffic / launch_s / 1e9, 1) if traffic else None,
+                     "traffic_frac": (round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic else None),
                      "algorithmic_bytes_per_launch": alg_bytes, "kernel": "march3_kernel",
                      "avg_launch_us": round(launch_s * 1e6, 2)},
         "norm_drift": norm - n_begin,

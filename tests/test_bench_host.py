@@ -38,3 +38,12 @@ def test_workload_line_shape():
     assert line["complex128"]["value"] == 1.0
     only = bench.workload_line({"c128": run(1.5)}, Args, "w", (8, 4), 10, 0.1)
     assert only["dtype"] == "c128" and "complex64" not in only and "complex128" not in only
+
+
+def test_3d_hash_covers_its_own_sources():
+    """The 3D counters are keyed by the code of the 3D march and of the 2D headers it
+    includes: a different key from the 2D one, stable across calls."""
+    assert set(bench.KERNEL_SOURCES[:2]) <= set(bench.KERNEL3_SOURCES)
+    h3 = bench.kernel_hash(bench.KERNEL3_SOURCES)
+    assert h3 == bench.kernel_hash(bench.KERNEL3_SOURCES) != bench.kernel_hash()
+    assert len(h3) == 16
