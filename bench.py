@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the second-order Trotter-Suzuki solve on one MI355X.
 
-Workload (one bench "step" = one whole solve of the hot path):
-  4096 x 4096 periodic mesh, four seeded Gaussian packets in a harmonic well
-  plus 32 seeded Gaussian bumps, dt = 0.05, 1000 second-order steps:
-  phase-table setup (FP64) + 1000 fused steps + FP64 norm/energy reduction.
-  Run in complex64 (headline line) and complex128 (nested object).
-Inputs are generated on the device before the timed region.  Prints ONE JSON
-line on stdout; progress goes to stderr.
+Default run (one JSON line on stdout; progress on stderr):
+  headline   32768 x 32768 periodic mesh, complex64 (8.6 GB state), four seeded
+             Gaussian packets in a harmonic well plus 32 seeded Gaussian bumps
+             (recipe scaled to the mesh), dt = 0.05, 200 second-order steps.
+             One bench "step" = one whole solve of the hot path: FP64 phase-table
+             setup + 200 fused steps + FP64 norm/energy reduction.
+  nested     the 4096^2 workload (1000 steps) in complex64 and complex128, the
+             256^2 complex128 well (100 steps), the batch of 512 uneven problems,
+             the served Poisson stream (p50/p99 latency), and the oracle timed on
+             the host cores (cpu_baseline), whose crops also check the headline's
+             result.
+Inputs are generated on the device before any timed region.  Other workloads:
+--workload (see --help).
 """
 from __future__ import annotations
 
@@ -98,33 +104,78 @@ def committed_traffic(dtype: str, schedule, nx: int, ny: int, nz: int = 0) -> fl
     return float(e["bytes_per_launch"])
 
 
-def run_dtype(dtype: str, p, psi0, V, args, order: int = 2, bc: str = "periodic"):
+def alg_bytes_per_site(dtype: str) -> int:
+    """Algorithmic HBM bytes per site of one fused pass: read psi, write psi and
+    read the phase factor, each in the working dtype (16 B complex128, 8 B
+    complex64)."""
+    return 3 * (16 if dtype == "c128" else 8)
+
+
+# Bytes per site the library's phase table holds: complex128 exp(-i phi) (16);
+# complex64 two 32-bit fixed-point parts (8).
+TABLE_BYTES_PER_SITE = {"c128": 16, "c64": 8}
+
+
+def roofline(dtype: str, sites: int, launch_s: float, site_steps_per_s: float, traffic,
+             kernel: str = "march_kernel") -> dict:
+    """Roofline object of one pass: algorithmic bytes per launch (SURVEY-style 3 x
+    elem per site) over the measured average launch time, against 8 TB/s."""
+    alg = sites * alg_bytes_per_site(dtype)
+    achieved = alg / launch_s / 1e9
+    elem = 16 if dtype == "c128" else 8
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": kernel, "avg_launch_us": round(launch_s * 1e6, 2),
+           "algorithmic_bytes_per_launch": alg,
+           "algorithmic_bytes_per_site": alg_bytes_per_site(dtype),
+           # table bytes the pass reads beyond the working dtype's size (0 for both)
+           "table_extra_bytes_per_launch": sites * (TABLE_BYTES_PER_SITE[dtype] - elem),
+           # one pass per step would move the algorithmic bytes every step: how
+           # far fusion takes the solve past that kernel's roofline (> 1)
+           "eff_frac_one_pass_per_step": round(site_steps_per_s * alg_bytes_per_site(dtype)
+                                               / (HBM_PEAK_GBS * 1e9), 3)}
+    if traffic:
+        out["traffic_source"] = ("rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel code, mesh "
+                                 "and schedule (profiles/traffic.json), not this run")
+        out["traffic_over_algorithmic"] = round(traffic / alg, 3)
+        out["traffic_GBps"] = round(traffic / launch_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def run_dtype(dtype: str, p, psi0, V, args, order: int = 2, bc: str = "periodic",
+              keep_result: bool = False):
+    """Tune, then time args.steps whole solves (phase table + p.steps fused steps
+    + FP64 observables) after args.warmup untimed ones; then one more solve from
+    psi0 for the precision figures (norm and energy before and after)."""
     import torch
     import paper_1208_2407_amd as tsq
     from paper_1208_2407_amd import autotune
 
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
-    psi = psi0.to(tdt).contiguous()
+    psi0 = psi0.to(tdt).contiguous()
+    psi = psi0.clone()
     plan = tsq.Plan(p.nx, p.ny, p.dt, dtype, order=order, bc=bc, device=psi.device)
     plan.set_potential(V)
+    tuning = None
     if args.schedule:
         plan.set_schedule(*[int(v) for v in args.schedule.split(",")])
     elif not args.no_tune:
-        sched, _ = autotune.tune(plan, psi, log=log if args.verbose else None)
-        log(f"{dtype}: autotuned schedule S={sched[0]} seg={sched[1]} ppl={sched[2]} "
-            f"store={sched[3]}")
+        sched, table = autotune.tune(plan, psi, log=log if args.verbose else None)
+        tuning = {"table_ms": table, "tie": autotune.TIE}
+        log(f"{dtype} {p.nx}x{p.ny}: autotuned schedule S={sched[0]} seg={sched[1]} "
+            f"ppl={sched[2]} store={sched[3]}")
     sched = plan.schedule()
     passes, copy_back = plan.passes(p.steps)
-    ws = plan.workspace()
-    n_begin, e_begin = plan.observables(psi, V)
+    stream = torch.cuda.current_stream()
 
     def solve(events=None):
         plan.set_potential(V)
         if events is not None:
-            events[0].record()
+            events[0].record(stream)
         plan.evolve(psi, p.steps)
         if events is not None:
-            events[1].record()
+            events[1].record(stream)
         return plan.observables(psi, V)
 
     for _ in range(args.warmup):
@@ -134,44 +185,55 @@ def run_dtype(dtype: str, p, psi0, V, args, order: int = 2, bc: str = "periodic"
            for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
-        norm, energy = solve(evs[k])
+        solve(evs[k])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    wall = time.perf_counter() - t0
     evolve_ms = sum(a.elapsed_time(b) for a, b in evs)
-    wall = t1 - t0
     site_steps = p.nx * p.ny * p.steps * args.steps
-    elem = 16 if dtype == "c128" else 8
-    alg_bytes = p.nx * p.ny * (2 * elem + 16)   # read psi, write psi, read phase table
     launch_s = evolve_ms * 1e-3 / (args.steps * passes)
-    achieved = alg_bytes / launch_s / 1e9
-    # counters were taken on second-order passes; fourth-order launches mix pass sizes
+    # counters were taken on second-order periodic passes only
     traffic = (committed_traffic(dtype, sched, p.nx, p.ny)
                if order == 2 and bc == "periodic" else None)
-    # one pass per step would need the same bytes every step: site-steps/s times those
-    # bytes over the peak says how far fusion takes the solve past that roofline (> 1)
-    eff_frac = (site_steps / wall) * (2 * elem + 16) / (HBM_PEAK_GBS * 1e9)
-    log(f"{dtype}: {wall / args.steps * 1e3:.2f} ms/solve, {site_steps / wall:.4e} site-steps/s, "
-        f"pass {launch_s * 1e6:.1f} us, {achieved:.0f} GB/s algorithmic, norm {norm:.15f}")
-    del ws
-    return {
+    # precision: one solve from the initial state
+    psi.copy_(psi0)
+    n0, e0 = plan.observables(psi, V)
+    n1, e1 = solve()
+    log(f"{dtype} {p.nx}x{p.ny}: {wall / args.steps * 1e3:.2f} ms/solve, "
+        f"{site_steps / wall:.4e} site-steps/s, pass {launch_s * 1e6:.1f} us, "
+        f"norm {n0:.15f} -> {n1:.15f}, energy {e0:.12f} -> {e1:.12f}")
+    out = {
         "value": site_steps / wall,
         "ms_per_step": wall / args.steps * 1e3,
         "schedule": {"steps_per_pass": sched[0], "segment_rows": sched[1],
                      "pairs_per_lane": sched[2],
                      "phase_store": {1: "registers", 2: "lds"}[sched[3]],
                      "passes_per_solve": passes, "copy_back": copy_back},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "traffic_GBps": round(traffic / launch_s / 1e9, 1) if traffic else None,
-                     "traffic_frac": (round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
-                                      if traffic else None),
-                     "eff_frac_one_pass_per_step": round(eff_frac, 3),
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel": "march_kernel", "avg_launch_us": round(launch_s * 1e6, 2)},
-        "norm_drift": norm - n_begin,
-        "energy": energy,
+        "roofline": roofline(dtype, p.nx * p.ny, launch_s, site_steps / wall, traffic),
+        "precision": {"norm_start": n0, "norm_end": n1, "norm_drift": n1 - n0,
+                      "energy_start": e0, "energy_end": e1, "energy_drift": e1 - e0},
     }
+    if tuning:
+        out["tuning"] = tuning
+    if keep_result:
+        out["psi"] = psi
+    else:
+        del psi
+    del plan
+    return out
+
+
+def vs_oracle(prec: dict, ref: dict) -> dict:
+    """GPU norm and energy (start and end of one solve) against the oracle's, from
+    the same starting values."""
+    return {"oracle_norm_drift": ref["norm_end"] - ref["norm_start"],
+            "oracle_energy_drift": ref["energy_end"] - ref["energy_start"],
+            "norm_end_minus_oracle": prec["norm_end"] - ref["norm_end"],
+            "energy_end_rel_diff": abs(prec["energy_end"] - ref["energy_end"])
+            / abs(ref["energy_end"]),
+            "energy_start_rel_diff": abs(prec["energy_start"] - ref["energy_start"])
+            / abs(ref["energy_start"]),
+            "oracle_source": "tests/golden/oracle_observables_4096.json (FP64 oracle, "
+                             "same workload and starting values)"}
 
 
 def run_td(dtype: str, p, psi0, V0, W, f, args, bc: str = "periodic"):
@@ -232,7 +294,8 @@ def run_td(dtype: str, p, psi0, V0, W, f, args, bc: str = "periodic"):
     evolve_ms = sum(a.elapsed_time(b) for a, b in evs)
     site_steps = p.nx * p.ny * len(f) * args.steps
     elem = 16 if dtype == "c128" else 8
-    alg_bytes = p.nx * p.ny * (2 * elem + 16)   # read psi, write psi, read (theta0, w)
+    # read psi, write psi, read (theta0, w): the potential's two FP64 parts per site
+    alg_bytes = p.nx * p.ny * (2 * elem + 16)
     launch_s = evolve_ms * 1e-3 / (args.steps * passes)
     achieved = alg_bytes / launch_s / 1e9
     log(f"td {dtype}: S={sched[0]} store={sched[3]}: {wall / args.steps * 1e3:.2f} ms/solve, "
@@ -244,9 +307,10 @@ def run_td(dtype: str, p, psi0, V0, W, f, args, bc: str = "periodic"):
                      "passes_per_solve": passes, "copy_back": copy_back},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "algorithmic_bytes_per_launch": alg_bytes, "kernel": "march_kernel (td)",
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "algorithmic_bytes_per_site": 2 * elem + 16, "kernel": "march_kernel (td)",
                      "avg_launch_us": round(launch_s * 1e6, 2)},
-        "norm_drift": norm - n_begin,
+        "precision": {"norm_drift": norm - n_begin},
     }
 
 
@@ -283,24 +347,16 @@ def run_3d(dtype: str, p, psi0, V, args):
     wall = time.perf_counter() - t0
     evolve_ms = sum(a.elapsed_time(b) for a, b in evs)
     site_steps = p.sites * p.steps * args.steps
-    elem = 16 if dtype == "c128" else 8
-    alg_bytes = p.sites * (2 * elem + 16)
     launch_s = evolve_ms * 1e-3 / (args.steps * passes)
-    achieved = alg_bytes / launch_s / 1e9
     traffic = committed_traffic(dtype, (1,), p.nx, p.ny, p.nz)
     log(f"3d {dtype}: {wall / args.steps * 1e3:.2f} ms/solve, {site_steps / wall:.4e} site-steps/s, "
-        f"pass {launch_s * 1e6:.1f} us, {achieved:.0f} GB/s algorithmic, norm {norm:.15f}")
+        f"pass {launch_s * 1e6:.1f} us, norm {norm:.15f}")
     return {
         "value": site_steps / wall, "ms_per_step": wall / args.steps * 1e3,
         "schedule": {"steps_per_pass": 1, "passes_per_solve": passes, "copy_back": copy_back},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_GBps": round(traffic / launch_s / 1e9, 1) if traffic else None,
-                     "traffic_frac": (round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
-                                      if traffic else None),
-                     "algorithmic_bytes_per_launch": alg_bytes, "kernel": "march3_kernel",
-                     "avg_launch_us": round(launch_s * 1e6, 2)},
-        "norm_drift": norm - n_begin,
+        "roofline": roofline(dtype, p.sites, launch_s, site_steps / wall, traffic,
+                             kernel="march3_kernel"),
+        "precision": {"norm_drift": norm - n_begin},
     }
 
 
@@ -338,7 +394,7 @@ def profile_mode(p, psi0, V, args) -> int:
         elem = 16 if d == "c128" else 8
         out["runs"][d] = {"schedule": list(sched), "steps": steps,
                           "passes": plan.passes(steps)[0],
-                          "algorithmic_bytes_per_launch": p.nx * p.ny * (2 * elem + 16)}
+                          "algorithmic_bytes_per_launch": p.nx * p.ny * alg_bytes_per_site(d)}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -363,7 +419,7 @@ def sweep_mode(p, psi0, V, args) -> int:
     for d in args.dtypes.split(","):
         tdt = torch.complex128 if d == "c128" else torch.complex64
         elem = 16 if d == "c128" else 8
-        alg = p.nx * p.ny * (2 * elem + 16)
+        alg = p.nx * p.ny * alg_bytes_per_site(d)
         for sched in cands:
             psi = psi0.to(tdt).clone()
             plan = tsq.Plan(p.nx, p.ny, p.dt, d, device=psi.device)
@@ -400,9 +456,11 @@ def sweep_mode(p, psi0, V, args) -> int:
 def run_batch(args) -> dict:
     """512 independent complex64 problems (sides log-uniform in [64, 1024], rounded to
     even; own potential, packets and dt), 500 steps each: one batched call (captured
-    HIP graph) against sequential plain tsq_evolve calls on the same GPU."""
+    HIP graph, schedule and tile height from the autotuner) against sequential plain
+    tsq_evolve calls on the same GPU."""
     import torch
     import paper_1208_2407_amd as tsq
+    from paper_1208_2407_amd import autotune
     from paper_1208_2407_amd import workloads as wl
 
     probs = wl.batch_problems(512, 4, 500, dtype="c64")
@@ -427,31 +485,22 @@ def run_batch(args) -> dict:
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    # batch schedule: a short search over steps per pass and phase ring (one pair per lane)
-    best = None
-    cands = ([tuple(int(v) for v in args.schedule.split(","))] if args.schedule
-             else [(S, 0, 1, st) for S in (3, 4, 5, 6) for st in (1, 2)])
-    for sched in cands:
-        psis = [x.clone() for x in psi0s]
-        bt = tsq.Batch(plans, psis, steps, sched)
-        bt.launch(use_graph=True)
-        t = timed(lambda: bt.launch(use_graph=True), 1)
-        log(f"batch: S={sched[0]} store={sched[3]}: {t * 1e3:.1f} ms per call "
-            f"({bt.info()[0]} launches)")
-        if best is None or t < best[0]:
-            best = (t, sched)
-        del bt, psis
-    sched = best[1]
+    if args.schedule:
+        sched, table = tuple(int(v) for v in args.schedule.split(",")), {}
+    else:
+        sched, table = autotune.tune_batch(plans, psi0s, steps,
+                                           log=log if args.verbose else None)
+    log(f"batch: schedule S={sched[0]} tile_rows={sched[1]} store={sched[3]}")
     psis = [x.clone() for x in psi0s]
     bt = tsq.Batch(plans, psis, steps, sched)
     launches, tiles = bt.info()
     for _ in range(args.warmup):
         bt.launch(use_graph=True)
     t_batch = timed(lambda: bt.launch(use_graph=True), args.steps)
-    # sequential plain solves: each problem alone, same kernels and schedule
+    # sequential plain solves: each problem alone, same kernels and steps per pass
     seq = [x.clone() for x in psi0s]
     for pl in plans:
-        pl.set_schedule(*sched)
+        pl.set_schedule(sched[0], 0, sched[2], sched[3])
 
     def sequential():
         for pl, x, n in zip(plans, seq, steps):
@@ -468,21 +517,28 @@ def run_batch(args) -> dict:
     bt1.launch()
     torch.cuda.synchronize()
     same = all(torch.equal(a, b) for a, b in zip(one[:8], ref))
+    # precision: the largest norm drift over the batch (FP64 reductions)
+    drift = 0.0
+    for pl, x, x0, V in zip(plans, one, psi0s, Vs):
+        n1, _ = pl.observables(x, V)
+        n0, _ = pl.observables(x0, V)
+        drift = max(drift, abs(n1 - n0))
     log(f"batch: {t_batch * 1e3:.1f} ms per call, sequential {t_seq * 1e3:.1f} ms, "
-        f"speedup {t_seq / t_batch:.2f}x, bitwise equal to alone: {same}")
+        f"speedup {t_seq / t_batch:.2f}x, bitwise equal to alone: {same}, "
+        f"max |norm drift| {drift:.2e}")
     return {
-        "metric": METRIC, "value": site_steps / t_batch, "unit": "site-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_batch * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
-        "data": "synthetic",
-        "config": {"workload": "batch512_c64_500steps", "problems": len(probs), "sites": sites,
-                   "site_steps_per_call": site_steps, "steps_per_pass": sched[0],
-                   "phase_store": "registers" if sched[3] == 1 else "lds",
-                   "launches_per_call": launches, "tiles_per_call": tiles,
-                   "hip_graph": True},
+        "workload": "batch512_c64_500steps", "value": site_steps / t_batch,
+        "unit": "site-steps/s", "ms_per_call": t_batch * 1e3, "calls_timed": args.steps,
+        "problems": len(probs), "sites": sites, "site_steps_per_call": site_steps,
+        "schedule": {"steps_per_pass": sched[0], "tile_rows": sched[1] or "auto",
+                     "phase_store": "registers" if sched[3] == 1 else "lds",
+                     "picked_by": "given" if args.schedule else "autotune.tune_batch"},
+        "tuning_table_ms": table,
+        "launches_per_call": launches, "tiles_per_call": tiles, "hip_graph": True,
         "sequential": {"value": site_steps / t_seq, "ms_per_call": t_seq * 1e3},
         "speedup_vs_sequential": t_seq / t_batch,
         "bitwise_equal_to_alone": same,
+        "precision": {"max_abs_norm_drift": drift},
     }
 
 
@@ -491,7 +547,6 @@ def run_served(args) -> dict:
     128-4096, steps 100-2000, 80/20 complex64/complex128) replayed in real time into
     the continuous-batching server; the FIFO one-at-a-time server on the first
     --fifo-seconds of the same trace for comparison."""
-    import torch
     from paper_1208_2407_amd import serve
     from paper_1208_2407_amd import workloads as wl
 
@@ -499,46 +554,110 @@ def run_served(args) -> dict:
     offered = sum(r.problem.site_steps for r in trace) / args.serve_seconds
     log(f"served: {len(trace)} requests over {args.serve_seconds} s, offered {offered:.3e} "
         f"site-steps/s")
-    # warm the code paths
-    serve.Server(block_steps=args.block_steps).run(trace[:16], realtime=False)
+    # schedules and block size from the autotuner on the trace's first requests
     srv = serve.Server(block_steps=args.block_steps)
+    if not args.block_steps:
+        srv.tune(trace[:200], log=log if args.verbose else None)
+    log(f"served: schedules {srv.schedules}, block {srv.block} steps")
+    # warm the code paths
+    serve.Server(block_steps=srv.block, schedules=srv.schedules).run(trace[:16], realtime=False)
     st = srv.run(trace, realtime=True).summary()
     log(f"served: {st}")
-    fifo_trace = [r for r in trace if r.arrival < args.fifo_seconds]
-    batched_prefix = serve.Server(block_steps=args.block_steps).run(fifo_trace).summary()
-    fifo = serve.serve_fifo(fifo_trace).summary()
-    log(f"served prefix ({args.fifo_seconds} s): batched {batched_prefix}")
-    log(f"served prefix ({args.fifo_seconds} s): fifo {fifo}")
-    return {
-        "metric": METRIC, "value": st["site_steps_per_s"], "unit": "site-steps/s", "n_gpus": 1,
-        "steps": 1, "warmup": 1, "ms_per_step": st["makespan_s"] * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+c128",
-        "data": "synthetic",
-        "config": {"workload": f"served_poisson200_{args.serve_seconds:g}s",
-                   "requests": len(trace), "offered_site_steps_per_s": offered,
-                   "block_steps": args.block_steps, "hbm_budget_bytes": srv.budget,
-                   "schedules": {k: list(v) for k, v in serve.SCHEDULES.items()}},
-        "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"],
+    out = {
+        "workload": f"served_poisson200_{args.serve_seconds:g}s", "requests": len(trace),
+        "offered_site_steps_per_s": offered, "value": st["site_steps_per_s"],
+        "unit": "site-steps/s", "latency_p50_s": st["p50_s"], "latency_p99_s": st["p99_s"],
         # 1.0 = the server kept up with the offered load (served everything as fast as
         # it arrived); below 1 the queue grew over the trace
         "served_over_offered": st["site_steps_per_s"] / offered if offered else None,
-        "served": st,
-        "fifo_comparison": {"trace_seconds": args.fifo_seconds, "batched": batched_prefix,
-                            "fifo": fifo},
+        "admitted": st["admitted"], "rejected": st["rejected"], "completed": st["completed"],
+        "block_steps": srv.block, "hbm_budget_bytes": srv.budget,
+        "schedules": srv.schedule_report(), "server": st,
+    }
+    if args.fifo_seconds > 0:
+        fifo_trace = [r for r in trace if r.arrival < args.fifo_seconds]
+        batched_prefix = serve.Server(block_steps=srv.block,
+                                      schedules=srv.schedules).run(fifo_trace).summary()
+        fifo = serve.serve_fifo(fifo_trace, schedules=srv.schedules).summary()
+        log(f"served prefix ({args.fifo_seconds} s): batched {batched_prefix}")
+        log(f"served prefix ({args.fifo_seconds} s): fifo {fifo}")
+        out["fifo_comparison"] = {"trace_seconds": args.fifo_seconds,
+                                  "batched": batched_prefix, "fifo": fifo}
+    return out
+
+
+def crops_of(p, psi0, V, width: int = 2048):
+    """Host copies (complex128 / float64) of `width`^2 windows of the device inputs,
+    one centred on each packet (corners on even sites)."""
+    n = p.nx
+    out = []
+    for q in p.packets:
+        yc = int(round(q.y0 / p.dy + p.ny / 2)) // 2 * 2
+        xc = int(round(q.x0 / p.dx + n / 2)) // 2 * 2
+        y0, x0 = yc - width // 2, xc - width // 2
+        out.append((y0, x0, psi0[y0:y0 + width, x0:x0 + width].cpu().numpy().astype("complex128"),
+                    V[y0:y0 + width, x0:x0 + width].cpu().numpy()))
+    return out
+
+
+def cpu_baseline(p, crops, results, one_core_steps: int) -> dict:
+    """The FP64 oracle on the host cores: the four 2048^2 crops of the headline
+    mesh (one centred on each packet), p.steps steps each, on every host thread,
+    and one crop for `one_core_steps` steps on one thread.  Each crop's interior
+    (a margin of the light cone 2N+1 plus one site per side) is compared with the
+    GPU's result of the same solve (`results`: the GPU interiors)."""
+    import numpy as np
+    import oracle
+
+    oracle.build(force=False)
+    cores = oracle.max_threads()
+    oracle.set_threads(cores)
+    t0 = time.perf_counter()
+    outs = [oracle.evolve(c, v, p.dt, p.steps) for (_, _, c, v) in crops]
+    t_all = time.perf_counter() - t0
+    w = crops[0][2].shape[0]
+    sites = sum(c.shape[0] * c.shape[1] for (_, _, c, _) in crops)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.evolve(crops[0][2], crops[0][3], p.dt, one_core_steps)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    m = 2 * p.steps + 2
+    errs = []
+    for want, got in zip(outs, results):
+        wi = want[m:w - m, m:w - m]
+        errs.append(float(np.linalg.norm(got - wi) / np.linalg.norm(wi)))
+    log(f"oracle: {cores} threads {sites * p.steps / t_all:.3e} site-steps/s ({t_all:.1f} s), "
+        f"1 thread {w * w * one_core_steps / t_one:.3e} ({t_one:.1f} s); crop interiors rel L2 "
+        + ", ".join(f"{e:.2e}" for e in errs))
+    return {
+        "baseline": {"value": sites * p.steps / t_all, "unit": "site-steps/s", "cores": cores,
+                     "kind": "oracle",
+                     "sample": f"the FP64 C oracle (OpenMP over lines) on four {w}x{w} crops of "
+                               f"the {p.nx}x{p.ny} mesh, one centred on each packet, {p.steps} "
+                               f"steps each ({t_all:.1f} s)",
+                     "one_core": {"value": w * w * one_core_steps / t_one, "cores": 1,
+                                  "sample": f"one {w}x{w} crop, {one_core_steps} steps "
+                                            f"({t_one:.1f} s)"}},
+        "crop_rel_l2": errs, "crop_interior": w - 2 * m,
     }
 
 
-def cpu_baseline(p, psi0_host, V_host, sample_steps: int):
-    import oracle
-    oracle.build(force=False)
-    cores = oracle.max_threads()
-    t0 = time.perf_counter()
-    oracle.evolve(psi0_host, V_host, p.dt, sample_steps)
-    dt = time.perf_counter() - t0
-    return {"value": p.nx * p.ny * sample_steps / dt, "unit": "site-steps/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{p.nx}x{p.ny} mesh of the same workload, first {sample_steps} of its "
-                      f"{p.steps} steps, FP64 C oracle (OpenMP over lines), {dt:.1f} s"}
+def dtype_entry(r: dict, **extra) -> dict:
+    """Nested JSON object of one dtype's run."""
+    out = {"value": r["value"], "unit": "site-steps/s", "ms_per_solve": r["ms_per_step"],
+           "schedule": r["schedule"], "roofline": r["roofline"], "precision": r["precision"]}
+    out.update(extra)
+    if "tuning" in r:
+        out["tuning"] = r["tuning"]
+    return out
+
+
+def line_head(args, value: float, ms: float, dtype: str, config: dict) -> dict:
+    return {"metric": METRIC, "value": value, "unit": "site-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
 
 
 def workload_line(res: dict, args, workload: str, mesh, steps: int, dt: float, **extra) -> dict:
@@ -546,52 +665,139 @@ def workload_line(res: dict, args, workload: str, mesh, steps: int, dt: float, *
     complex64 at the top level when it was measured, the other dtype nested."""
     head = "c64" if "c64" in res else next(iter(res))
     r = res[head]
-    line = {"metric": METRIC, "value": r["value"], "unit": "site-steps/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,
-            "data": "synthetic",
-            "config": {"workload": workload, "mesh": list(mesh), "time_steps_per_solve": steps,
-                       "dt": dt, **extra, **r["schedule"]},
-            "roofline": r["roofline"], "norm_drift": r["norm_drift"]}
+    line = line_head(args, r["value"], r["ms_per_step"], head,
+                     {"workload": workload, "mesh": list(mesh), "time_steps_per_solve": steps,
+                      "dt": dt, **extra, **r["schedule"]})
+    line["roofline"] = r["roofline"]
+    line["precision"] = r["precision"]
     for d, rr in res.items():
         if d != head:
-            line["complex128" if d == "c128" else "complex64"] = {
-                "dtype": d, "value": rr["value"], "unit": "site-steps/s",
-                "ms_per_step": rr["ms_per_step"], "config": rr["schedule"],
-                "roofline": rr["roofline"], "norm_drift": rr["norm_drift"]}
+            line["complex128" if d == "c128" else "complex64"] = dtype_entry(rr)
+    return line
+
+
+ORACLE_OBSERVABLES = os.path.join(ROOT, "tests", "golden", "oracle_observables_4096.json")
+
+
+def default_run(args) -> dict:
+    """The default benchmark line: the 32768^2 complex64 headline with the 4096^2
+    (both dtypes), 256^2, batched and served workloads nested, and the oracle."""
+    import torch
+    from paper_1208_2407_amd import workloads as wl
+
+    t_start = time.perf_counter()
+    p = wl.config("mesh32768_c64")
+    log(f"headline: generating the {p.nx}x{p.ny} inputs on the device")
+    psi0 = wl.initial_state(p, device="cuda", dtype=torch.complex64)
+    V = wl.potential(p, device="cuda")
+    torch.cuda.synchronize()
+    crops = [] if args.no_cpu_baseline else crops_of(p, psi0, V)
+    r = run_dtype("c64", p, psi0, V, args, keep_result=True)
+    m = 2 * p.steps + 2
+    interiors = []
+    for (y0, x0, c, _) in crops:
+        w = c.shape[0]
+        interiors.append(r["psi"][y0 + m:y0 + w - m, x0 + m:x0 + w - m].cpu().numpy()
+                         .astype("complex128"))
+    del r["psi"], psi0, V
+    torch.cuda.empty_cache()
+    line = line_head(args, r["value"], r["ms_per_step"], "c64",
+                     {"workload": "packets_bumps_32768x32768_dt0.05_200steps",
+                      "mesh": [p.nx, p.ny], "time_steps_per_solve": p.steps, "dt": p.dt,
+                      "boundary": "periodic",
+                      "step": "one solve: FP64 phase table, 200 fused steps, FP64 norm and "
+                              "energy", **r["schedule"]})
+    line["roofline"] = r["roofline"]
+    line["precision"] = r["precision"]
+    if "tuning" in r:
+        line["tuning"] = r["tuning"]
+    log(f"headline done ({time.perf_counter() - t_start:.0f} s)")
+
+    # the 4096^2 workload, both dtypes, against the oracle's norm and energy
+    p2 = wl.packets_and_bumps(4096, 4096, 2, 0.05, 1000, "c64", name="packets_bumps_4096")
+    psi02 = wl.initial_state(p2, device="cuda")
+    V2 = wl.potential(p2, device="cuda")
+    try:
+        with open(ORACLE_OBSERVABLES) as f:
+            ref = json.load(f)["inputs"]
+    except (OSError, ValueError, KeyError):
+        ref = {}
+    nested = {"workload": "packets_bumps_4096x4096_dt0.05_1000steps", "mesh": [4096, 4096],
+              "time_steps_per_solve": p2.steps, "dt": p2.dt}
+    for d in ("c64", "c128"):
+        rr = run_dtype(d, p2, psi02, V2, args)
+        if d in ref:
+            rr["precision"]["vs_oracle"] = vs_oracle(rr["precision"], ref[d])
+        nested[d] = dtype_entry(rr)
+    line["mesh4096"] = nested
+    del psi02, V2
+    # the 256^2 well, complex128 (its 1 MiB state stays in the caches: no HBM figure)
+    p1 = wl.gaussian_in_well(dtype="c128")
+    r1 = run_dtype("c128", p1, wl.initial_state(p1, device="cuda"), wl.potential(p1, device="cuda"),
+                   args)
+    r1["roofline"] = {"note": "1 MiB state held in L2 and the Infinity Cache: no HBM "
+                              "roofline", "avg_launch_us": r1["roofline"]["avg_launch_us"]}
+    line["mesh256"] = dtype_entry(r1, workload="gaussian_well_256x256_dt0.1_100steps",
+                                  dtype="c128")
+    torch.cuda.empty_cache()
+    log(f"nested meshes done ({time.perf_counter() - t_start:.0f} s)")
+    if not args.no_batch:
+        line["batch512"] = run_batch(args)
+        torch.cuda.empty_cache()
+        log(f"batch done ({time.perf_counter() - t_start:.0f} s)")
+    if not args.no_served:
+        line["served"] = run_served(args)
+        torch.cuda.empty_cache()
+        log(f"served done ({time.perf_counter() - t_start:.0f} s)")
+    if crops:
+        log("timing the oracle on the crops of the headline mesh")
+        cb = cpu_baseline(p, crops, interiors, args.cpu_one_core_steps)
+        line["cpu_baseline"] = cb["baseline"]
+        line["precision"]["vs_oracle_crops"] = {
+            "rel_l2": cb["crop_rel_l2"], "interior": cb["crop_interior"],
+            "note": "GPU complex64 result of the precision solve against the FP64 oracle on "
+                    "2048^2 crops centred on the four packets, compared on the interior their "
+                    "edges cannot reach in 200 steps"}
+    log(f"bench done ({time.perf_counter() - t_start:.0f} s)")
     return line
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed solves")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed solves")
+    ap.add_argument("--steps", type=int, default=5, help="timed solves (calls) per workload")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed solves per workload")
     ap.add_argument("--schedule", default="",
                     help="S,segment_rows,pairs_per_lane,phase_store (skip tuning)")
     ap.add_argument("--profile-passes", type=int, default=0,
-                    help="counter-collection mode: per dtype run exactly this many fused "
-                         "passes under --schedule, plus one device copy of 1 GiB (known "
-                         "bytes) to scale the HBM counters; prints a short JSON and exits. "
-                         "With --schedule sweep: every candidate schedule, each timed")
+                    help="counter-collection mode (mesh4096 and mesh32768 workloads): per "
+                         "dtype run exactly this many fused passes under --schedule, plus one "
+                         "device copy of 1 GiB (known bytes) to scale the HBM counters; prints "
+                         "a short JSON and exits.  With --schedule sweep: every candidate "
+                         "schedule, each timed")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=400)
+    ap.add_argument("--no-batch", action="store_true", help="default run: skip the batch")
+    ap.add_argument("--no-served", action="store_true", help="default run: skip the stream")
+    ap.add_argument("--cpu-one-core-steps", type=int, default=40)
     ap.add_argument("--dtypes", default="c64,c128")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", default="mesh4096",
-                    choices=["mesh4096", "mesh32768", "batch512", "served", "td4096", "mesh3d512",
-                             "order4_4096", "closed4096", "td_closed4096"],
-                    help="mesh4096: the benchmark line; mesh32768: 32768^2 complex64, 200 "
-                         "steps; batch512: 512 uneven complex64 problems, 500 steps; "
-                         "served: Poisson request stream into the batching server; td4096: "
-                         "the 4096^2 workload under a time-dependent potential; mesh3d512: "
-                         "512^3 packet in a harmonic well, 100 steps; order4_4096: the 4096^2 "
-                         "workload under the fourth-order product, 200 steps; closed4096: the 4096^2 "
-                         "workload between hard walls; td_closed4096: td4096 between hard walls")
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "mesh4096", "mesh32768", "batch512", "served", "td4096",
+                             "mesh3d512", "order4_4096", "closed4096", "td_closed4096"],
+                    help="default: the 32768^2 complex64 headline with every other benchmark "
+                         "workload nested; mesh4096: the 4096^2 workload alone; mesh32768: the "
+                         "32768^2 complex64 mesh alone (200 steps); batch512: 512 uneven "
+                         "complex64 problems, 500 steps; served: Poisson request stream into the "
+                         "batching server; td4096: the 4096^2 workload under a time-dependent "
+                         "potential; mesh3d512: 512^3 packet in a harmonic well, 100 steps; "
+                         "order4_4096: the 4096^2 workload under the fourth-order product, 200 "
+                         "steps; closed4096: the 4096^2 workload between hard walls; "
+                         "td_closed4096: td4096 between hard walls")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
-    ap.add_argument("--fifo-seconds", type=float, default=10.0)
-    ap.add_argument("--block-steps", type=int, default=20)
+    ap.add_argument("--fifo-seconds", type=float, default=5.0)
+    ap.add_argument("--block-steps", type=int, default=0,
+                    help="served: steps per scheduler iteration (0 = the tuned value)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the library has no multi-GPU path "
@@ -604,17 +810,32 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.workload == "default" and not args.profile_passes:
+        print(json.dumps(default_run(args)), flush=True)
+        return 0
     if args.workload == "batch512":
-        print(json.dumps(run_batch(args)), flush=True)
+        r = run_batch(args)
+        line = line_head(args, r["value"], r["ms_per_call"], "c64",
+                         {"workload": r["workload"], "problems": r["problems"]})
+        line.update({k: v for k, v in r.items() if k not in ("value", "workload", "unit")})
+        print(json.dumps(line), flush=True)
         return 0
     if args.workload == "served":
-        print(json.dumps(run_served(args)), flush=True)
+        r = run_served(args)
+        line = line_head(args, r["value"], r["server"]["makespan_s"] * 1e3, "c64+c128",
+                         {"workload": r["workload"], "requests": r["requests"]})
+        line.update({k: v for k, v in r.items() if k not in ("value", "workload", "unit")})
+        print(json.dumps(line), flush=True)
         return 0
     if args.workload == "mesh32768":
         p = wl.config("mesh32768_c64")
         log("generating inputs on the device")
         psi0 = wl.initial_state(p, device="cuda", dtype=torch.complex64)
         V = wl.potential(p, device="cuda")
+        if args.profile_passes and args.schedule == "sweep":
+            return sweep_mode(p, psi0, V, args)
+        if args.profile_passes:
+            return profile_mode(p, psi0, V, args)
         res = {"c64": run_dtype("c64", p, psi0, V, args)}
         line = workload_line(res, args, "packets_bumps_32768x32768_dt0.05_200steps", (p.nx, p.ny),
                              p.steps, p.dt)
@@ -672,49 +893,13 @@ def main() -> int:
     psi0 = wl.initial_state(p, device="cuda")
     V = wl.potential(p, device="cuda")
     torch.cuda.synchronize()
-
     if args.profile_passes and args.schedule == "sweep":
         return sweep_mode(p, psi0, V, args)
     if args.profile_passes:
         return profile_mode(p, psi0, V, args)
-
-    res = {}
-    for d in args.dtypes.split(","):
-        res[d] = run_dtype(d, p, psi0, V, args)
-
-    head = "c64" if "c64" in res else next(iter(res))
-    r = res[head]
-    line = {
-        "metric": METRIC,
-        "value": r["value"],
-        "unit": "site-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": r["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": head,
-        "data": "synthetic",
-        "config": {"workload": "packets_bumps_4096x4096_dt0.05_1000steps", "mesh": [p.nx, p.ny],
-                   "time_steps_per_solve": p.steps, "dt": p.dt, "boundary": "periodic",
-                   **r["schedule"]},
-        "roofline": r["roofline"],
-        "norm_drift": r["norm_drift"],
-    }
-    for d, rr in res.items():
-        if d == head:
-            continue
-        line[f"{'complex128' if d == 'c128' else 'complex64'}"] = {
-            "dtype": d, "value": rr["value"], "unit": "site-steps/s",
-            "ms_per_step": rr["ms_per_step"], "config": rr["schedule"],
-            "roofline": rr["roofline"], "norm_drift": rr["norm_drift"]}
-    if not args.no_cpu_baseline:
-        log("timing the oracle on a bounded sample")
-        psi_h = wl.initial_state(p).numpy()
-        V_h = V.cpu().numpy()
-        line["cpu_baseline"] = cpu_baseline(p, psi_h, V_h, args.cpu_sample_steps)
+    res = {d: run_dtype(d, p, psi0, V, args) for d in args.dtypes.split(",")}
+    line = workload_line(res, args, "packets_bumps_4096x4096_dt0.05_1000steps", (p.nx, p.ny),
+                         p.steps, p.dt, boundary="periodic")
     print(json.dumps(line), flush=True)
     return 0
 

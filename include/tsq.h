@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define TSQ_ABI_VERSION 4
+#define TSQ_ABI_VERSION 5
 
 typedef enum {
     TSQ_OK = 0,
@@ -102,12 +102,18 @@ int tsq_abi_version(void);
  * pointer stays valid until the next tsq_* call on the same thread. */
 const char* tsq_last_error(void);
 
-/* Validate a problem and build a plan: the FP64 rotation coefficients
- * (sin al and 1 - cos al = 2 sin^2(al/2) for tau = dt/2 and dt along each
- * axis) and a default schedule.  Host only; touches no device.
+/* Validate a problem and build a plan: the FP64 coefficients of the 2x2
+ * block exponentials of the hopping parts H1 and H2 (Sec. 2: each block
+ * [[0, V], [V, 0]], V = -hbar^2/(2 m a^2), exponentiates to a plane rotation
+ * by al = tau |V| / hbar) for tau = dt/2 and dt along each axis, and a default
+ * schedule.  Host only; touches no device.
+ * Periodic 2D meshes apply the rotations in a tangent form (see
+ * tsq_evolve) and accept |dt| hbar / (2 m da^2) < 1 rad per step along each
+ * axis (larger steps are far outside the product's accuracy anyway).
  * Errors: TSQ_ERR_ARG (null, bad constant, order not 0/2/4), TSQ_ERR_SHAPE,
  * TSQ_ERR_DTYPE, TSQ_ERR_UNSUPPORTED (a 3D mesh with closed boundaries or
- * order 4).  *out is set only on TSQ_OK. */
+ * order 4; a periodic 2D time step beyond that angle).  *out is set only on
+ * TSQ_OK. */
 int tsq_plan_create(const tsq_problem* problem, tsq_plan** out);
 
 /* Free a plan (NULL is accepted). */
@@ -139,9 +145,9 @@ typedef struct {
 /* Set the plan's schedule (host only).  Zero fields take their defaults;
  * tsq_plan_get_schedule returns the resolved values (segment_rows stays 0 when
  * it is sized per launch).  Errors: TSQ_ERR_ARG (null, value out of range, or
- * an unsupported combination: registers with more than 4 steps per pass, LDS
- * with 2 pairs per lane, 2 pairs per lane on a closed mesh); the plan keeps
- * its previous schedule. */
+ * an unsupported combination: registers with more than 6 steps per pass, or
+ * more than 4 with 2 pairs per lane; LDS with 2 pairs per lane; 2 pairs per
+ * lane on a closed mesh); the plan keeps its previous schedule. */
 int tsq_plan_set_schedule(tsq_plan* plan, const tsq_schedule* schedule);
 int tsq_plan_get_schedule(const tsq_plan* plan, tsq_schedule* schedule);
 
@@ -151,16 +157,25 @@ int tsq_plan_get_schedule(const tsq_plan* plan, tsq_schedule* schedule);
  * (odd pass count that cannot be split).  Host only.  Errors: TSQ_ERR_ARG. */
 int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int32_t* copy_back);
 
-/* Row a0: build the phase table exp(-i dt (V_l + eps0) / hbar) in FP64 from
- * the device array V_dev (nx*ny doubles) into the workspace `ws` of
- * `ws_bytes` bytes (device, 256-byte aligned), rounded to the plan's dtype.
+/* The diagonal part H0 of Sec. 2 (potential plus the mesh's on-site term
+ * eps_l = V_l + hbar^2/(m a^2) per axis) acts through exp(-i dt eps_l / hbar):
+ * build that phase table exp(-i dt (V_l + eps0) / hbar) in FP64 from the device
+ * array V_dev (nx*ny doubles) into the workspace `ws` of `ws_bytes` bytes
+ * (device, 256-byte aligned), rounded to the plan's dtype (complex64: a hi + lo
+ * pair of complex floats, exp = hi + lo to about 48 bits).
  * Records `ws`; tsq_evolve must be given the same workspace.
  * Errors: TSQ_ERR_ARG (null), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
 int tsq_set_potential(tsq_plan* plan, const double* V_dev, void* ws, size_t ws_bytes,
                       void* stream);
 
-/* Rows a1-a6: apply U2(dt)^steps (order 4: U4(dt)^steps) to psi_dev in place (device, contiguous,
- * 16-byte aligned).  steps == 0 returns TSQ_OK without a launch.
+/* Apply the second-order product U2(dt) of Eq. "secondorder" `steps` times
+ * (order 4: U4(dt) of Eq. "fourthorder") to psi_dev in place (device,
+ * contiguous, 16-byte aligned): several steps are fused per read and write of
+ * psi (the schedule's steps_per_pass), consecutive odd factors merged.  On
+ * periodic 2D meshes the even and odd-y factors rotate in the tangent form
+ * (a, b) <- (a + i t b, b + i t a), t = tan al, and the odd-x factor of each step
+ * restores the product of the cosines; equal to the block exponentials in real
+ * arithmetic.  steps == 0 returns TSQ_OK without a launch.
  * Errors: TSQ_ERR_ARG (null, steps < 0, misaligned psi), TSQ_ERR_STATE (no
  * potential set, a different workspace, or a time-dependent table from
  * tsq_set_potential_td), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
@@ -196,8 +211,9 @@ int tsq_set_potential_td(tsq_plan* plan, const double* V0_dev, const double* W_d
 int tsq_evolve_td(tsq_plan* plan, void* psi_dev, int64_t steps, const double* f_host, void* ws,
                   size_t ws_bytes, void* stream);
 
-/* Row a7: FP64 norm N = sum |psi_l|^2 and energy E = <psi|H|psi> / N of the
- * lattice Hamiltonian H = diag(V + eps0) - Jx (x-neighbours) - Jy
+/* FP64 norm N = sum |psi_l|^2, the quantity the unitary product conserves
+ * (Sec. 2: |<psi|psi>| = 1), and energy E = <psi|H|psi> / N of the mesh
+ * Hamiltonian of Sec. 2, H = diag(V + eps0) - Jx (x-neighbours) - Jy
  * (y-neighbours), J_a = hbar^2/(2 m da^2), neighbours wrapping periodically
  * (absent beyond closed walls).
  * Reduces in a fixed order (bitwise reproducible), uses the scratch part of
@@ -222,8 +238,9 @@ typedef struct tsq_batch tsq_batch; /* opaque, host memory */
  * called with that workspace) for steps[i] >= 0 steps.  All plans must have
  * the same dtype and be periodic and of order 2, with a time-independent
  * potential on a 2D mesh (else TSQ_ERR_UNSUPPORTED).
- * `schedule` (NULL = defaults; segment_rows is ignored, the
- * batch sizes its own tiles) applies to every problem.  The batch records the
+ * `schedule` (NULL = defaults) applies to every problem; its segment_rows
+ * is the height in rows of the batch's tiles (even; 0 = sized so one launch
+ * is about one tile per resident wavefront).  The batch records the
  * device pointers, which must stay valid while it is used; plans may be
  * destroyed afterwards.  Errors: TSQ_ERR_ARG, TSQ_ERR_DTYPE (mixed dtypes),
  * TSQ_ERR_STATE (a plan without potential or with another workspace),
@@ -252,6 +269,22 @@ int tsq_batch_upload(tsq_batch* batch, void* bws, size_t bws_bytes, void* stream
  * Each call advances every problem by its step count again.
  * Errors: TSQ_ERR_STATE (not uploaded), TSQ_ERR_ARG, TSQ_ERR_DEVICE. */
 int tsq_batch_launch(tsq_batch* batch, int32_t use_graph, void* stream);
+
+/* One call for the batched form: advance problem i (plans[i] on psi_dev[i]
+ * with workspace ws[i], as for tsq_batch_create) by steps[i] steps, all
+ * problems together, asynchronously on `stream`.  The work lists go to the
+ * caller's device buffer `bws` of `bws_bytes` bytes (256-byte aligned, at least
+ * what tsq_batch_evolve_workspace_size returns for the same arguments), which
+ * must stay untouched until the work on `stream` has finished.  Equivalent to
+ * tsq_batch_create + tsq_batch_upload + tsq_batch_launch (no graph) +
+ * tsq_batch_destroy; results are bitwise identical to tsq_evolve of each
+ * problem alone with the same schedule.  Errors: those of the four calls. */
+int tsq_batch_evolve_workspace_size(tsq_plan* const* plans, void* const* psi_dev,
+                                    void* const* ws, const int64_t* steps, int32_t n,
+                                    const tsq_schedule* schedule, size_t* bytes);
+int tsq_batch_evolve(tsq_plan* const* plans, void* const* psi_dev, void* const* ws,
+                     const int64_t* steps, int32_t n, const tsq_schedule* schedule, void* bws,
+                     size_t bws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,8 @@ EXPORTED = ("tsq_abi_version", "tsq_last_error", "tsq_plan_create", "tsq_plan_de
             "tsq_evolve_passes", "tsq_set_potential", "tsq_evolve", "tsq_set_potential_td",
             "tsq_evolve_td", "tsq_observables",
             "tsq_batch_create", "tsq_batch_destroy", "tsq_batch_workspace_size", "tsq_batch_info",
-            "tsq_batch_upload", "tsq_batch_launch")
+            "tsq_batch_upload", "tsq_batch_launch", "tsq_batch_evolve_workspace_size",
+            "tsq_batch_evolve")
 
 
 class TsqError(RuntimeError):
@@ -101,6 +102,11 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.tsq_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.tsq_batch_upload.argtypes = [vp, vp, sz, vp]
     lib.tsq_batch_launch.argtypes = [vp, i32, vp]
+    lib.tsq_batch_evolve_workspace_size.argtypes = [vpp, vpp, vpp, ctypes.POINTER(i64), i32,
+                                                    ctypes.POINTER(tsq_schedule),
+                                                    ctypes.POINTER(sz)]
+    lib.tsq_batch_evolve.argtypes = [vpp, vpp, vpp, ctypes.POINTER(i64), i32,
+                                     ctypes.POINTER(tsq_schedule), vp, sz, vp]
     for name in EXPORTED[2:]:
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
@@ -217,6 +223,30 @@ def tsq_batch_upload(batch: int, bws: int, nbytes: int, stream: int) -> None:
 
 def tsq_batch_launch(batch: int, use_graph: bool, stream: int) -> None:
     _check(load_library().tsq_batch_launch(batch, 1 if use_graph else 0, stream))
+
+
+def _batch_args(plans, psi_devs, wss, steps):
+    n = len(plans)
+    arr = lambda xs: (ctypes.c_void_p * n)(*xs)
+    return arr(plans), arr(psi_devs), arr(wss), (ctypes.c_int64 * n)(*[int(v) for v in steps]), n
+
+
+def tsq_batch_evolve_workspace_size(plans, psi_devs, wss, steps,
+                                    schedule: Optional[tsq_schedule] = None) -> int:
+    a, b, c, st, n = _batch_args(plans, psi_devs, wss, steps)
+    out = ctypes.c_size_t()
+    _check(load_library().tsq_batch_evolve_workspace_size(
+        a, b, c, st, n, ctypes.byref(schedule) if schedule is not None else None,
+        ctypes.byref(out)))
+    return out.value
+
+
+def tsq_batch_evolve(plans, psi_devs, wss, steps, schedule: Optional[tsq_schedule], bws: int,
+                     bws_bytes: int, stream: int) -> None:
+    a, b, c, st, n = _batch_args(plans, psi_devs, wss, steps)
+    _check(load_library().tsq_batch_evolve(
+        a, b, c, st, n, ctypes.byref(schedule) if schedule is not None else None, bws, bws_bytes,
+        stream))
 
 
 # ---------------------------------------------------------------- convenience layer

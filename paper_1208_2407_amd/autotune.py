@@ -28,7 +28,7 @@ DEFAULT_CANDIDATES: List[Schedule] = (
 
 
 # relative time difference below which two schedules count as equally fast
-TIE = 0.01
+TIE = 0.02
 
 
 def cache_path() -> str:
@@ -96,12 +96,21 @@ def pick(timed: List[Tuple[float, Schedule]], tie: float = TIE) -> Schedule:
     return min(near)[2]
 
 
+# Segment heights tried around the one-round default (rows; those taller than the
+# mesh are skipped).
+SEGMENT_ROWS: List[int] = [32, 64, 128, 256, 512, 1024, 2048, 4096, 8192]
+
+
 def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: int = 120,
-         use_cache: bool = True, log=None) -> Tuple[Schedule, Dict[str, float]]:
+         use_cache: bool = True, segments: bool = True, log=None
+         ) -> Tuple[Schedule, Dict[str, float]]:
     """Pick the fastest schedule for this plan's mesh and dtype; set it on the plan.
 
+    Two stages: steps per pass and phase store at the one-round segment height
+    (segment_rows 0), then the segment height (SEGMENT_ROWS, tile shape along y)
+    for the winner, which keeps 0 unless another height is faster beyond `TIE`.
     `psi` is not modified (a scratch copy is evolved).  Returns the schedule and
-    the timing table {"S,seg,ppl": ms}."""
+    the timing table {"S,seg,ppl,store": ms}."""
     import torch
     arch = torch.cuda.get_device_properties(psi.device).gcnArchName.split(":")[0]
     key = _key(arch, plan.dtype, plan.problem.nx, plan.problem.ny, plan.problem.order,
@@ -114,17 +123,207 @@ def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: i
     scratch = psi.clone()
     table: Dict[str, float] = {}
     timed: List[Tuple[float, Schedule]] = []
-    for cand in (candidates or DEFAULT_CANDIDATES):
+
+    def run(cand):
         ms = time_schedule(plan, scratch, cand, steps)
         table[",".join(map(str, cand))] = ms
         timed.append((ms, tuple(cand)))
         if log:
             log(f"autotune {key} S={cand[0]} seg={cand[1]} ppl={cand[2]} store={cand[3]}: "
                 f"{ms:.3f} ms")
-    del scratch
+        return ms
+
+    for cand in (candidates or DEFAULT_CANDIDATES):
+        run(cand)
     best = pick(timed)
+    if segments and candidates is None:
+        base = next(ms for ms, c in timed if c == best)
+        seg_timed = [(base, best)]
+        for rows in SEGMENT_ROWS:
+            if rows >= plan.problem.ny:
+                continue
+            cand = (best[0], rows, best[2], best[3])
+            seg_timed.append((run(cand), cand))
+        # another height only if it beats the one-round default beyond the tie
+        fastest = min(seg_timed)
+        if fastest[0] < base * (1.0 - TIE):
+            best = fastest[1]
+    del scratch
     plan.set_schedule(*best)
     if use_cache:
         db[key] = {"schedule": list(best), "table": table, "steps": steps}
         _store(db)
     return best, table
+
+
+# ---------------------------------------------------------------- batched form
+
+# steps per pass x phase store (one pair per lane), then the tile height
+BATCH_CANDIDATES: List[Schedule] = [(S, 0, 1, store) for S in (3, 4, 5, 6) for store in (1, 2)]
+BATCH_TILE_ROWS: List[int] = [32, 64, 128, 256, 512, 1024]
+
+
+def signature(dtype: str, shapes) -> str:
+    """Workload signature of a batch: dtype and a hash of its sorted (nx, ny, steps)."""
+    import hashlib
+    items = sorted((int(a), int(b), int(c)) for a, b, c in shapes)
+    h = hashlib.sha256(repr(items).encode()).hexdigest()[:16]
+    return f"{dtype}|n{len(items)}|{h}"
+
+
+def batch_signature(plans, steps) -> str:
+    return signature(plans[0].dtype, [(pl.problem.nx, pl.problem.ny, n)
+                                      for pl, n in zip(plans, steps)])
+
+
+def time_batch(plans, psis, steps, schedule: Schedule, repeats: int = 2) -> float:
+    """Best-of-`repeats` milliseconds of one graph-replayed call of a Batch of
+    `plans` over `psis` under `schedule` (the first call captures the graph)."""
+    import torch
+    from . import Batch
+    bt = Batch(plans, psis, steps, schedule)
+    bt.launch(use_graph=True)
+    best = float("inf")
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bt.launch(use_graph=True)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del bt
+    return best
+
+
+def tune_batch(plans, psi0s, steps, *, candidates: Optional[Iterable[Schedule]] = None,
+               tile_rows: Optional[Iterable[int]] = None, use_cache: bool = True, log=None
+               ) -> Tuple[Schedule, Dict[str, float]]:
+    """Pick the batch schedule (steps per pass, phase store, then tile height in
+    segment_rows) for these problems: times graph-replayed batched calls on
+    scratch copies of `psi0s`; caches by device, workload signature and library."""
+    import torch
+    arch = torch.cuda.get_device_properties(psi0s[0].device).gcnArchName.split(":")[0]
+    key = f"{arch}|batch|{batch_signature(plans, steps)}|{_library_stamp()}"
+    db = _load() if use_cache else {}
+    if use_cache and key in db and len(db[key].get("schedule", [])) == 4:
+        return tuple(db[key]["schedule"]), db[key].get("table", {})
+    psis = [x.clone() for x in psi0s]
+    table: Dict[str, float] = {}
+    timed: List[Tuple[float, Schedule]] = []
+
+    def run(cand):
+        ms = time_batch(plans, psis, steps, cand)
+        table[",".join(map(str, cand))] = ms
+        timed.append((ms, tuple(cand)))
+        if log:
+            log(f"autotune batch S={cand[0]} tile_rows={cand[1]} store={cand[3]}: {ms:.3f} ms")
+        return ms
+
+    for cand in (candidates or BATCH_CANDIDATES):
+        run(cand)
+    best = min(timed)[1]
+    base = min(timed)[0]
+    rows_timed = [(base, best)]
+    for rows in (tile_rows if tile_rows is not None else BATCH_TILE_ROWS):
+        cand = (best[0], int(rows), best[2], best[3])
+        rows_timed.append((run(cand), cand))
+    fastest = min(rows_timed)
+    if fastest[0] < base * (1.0 - TIE):
+        best = fastest[1]
+    del psis
+    if use_cache:
+        db[key] = {"schedule": list(best), "table": table}
+        _store(db)
+    return best, table
+
+
+# ---------------------------------------------------------------- served form
+
+SERVE_CANDIDATES: List[Schedule] = [(S, 0, 1, store) for S in (4, 5, 6) for store in (1, 2)]
+SERVE_BLOCKS: List[int] = [10, 20, 40]
+# a smaller block (finer scheduling, earlier admission) is kept while its
+# throughput stays within this fraction of the best block's
+SERVE_BLOCK_SLACK = 0.05
+
+
+def time_block(plans, psis, steps, schedule: Schedule, repeats: int = 2) -> float:
+    """Best-of-`repeats` wall milliseconds of one scheduler iteration as the
+    server runs it: build a Batch (host work lists, upload), launch it eagerly,
+    wait for it."""
+    import time as _time
+    import torch
+    from . import Batch
+    best = float("inf")
+    for _ in range(repeats + 1):
+        torch.cuda.synchronize()
+        t0 = _time.perf_counter()
+        bt = Batch(plans, psis, steps, schedule)
+        bt.launch()
+        torch.cuda.synchronize()
+        ms = (_time.perf_counter() - t0) * 1e3
+        del bt
+        best = min(best, ms)
+    return best
+
+
+def tune_serve(sample, device="cuda", *, per_dtype: int = 16, use_cache: bool = True,
+               log=None) -> dict:
+    """Schedule per dtype and steps per scheduler iteration for the server, from a
+    sample of requests (the first `per_dtype` of each dtype): every (schedule,
+    block) advances all sampled problems of a dtype together, timed as the server
+    runs an iteration; the schedule with the highest site-steps/s wins, and the
+    block is the smallest within SERVE_BLOCK_SLACK of the best block's rate."""
+    import torch
+    from . import Plan
+    from . import workloads as wl
+    arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+    out = {"schedules": {}, "table": {}}
+    block_votes: List[int] = []
+    for dtype in ("c64", "c128"):
+        reqs = [r for r in sample if r.problem.dtype == dtype][:per_dtype]
+        if not reqs:
+            continue
+        sig = signature(dtype, [(r.problem.nx, r.problem.ny, r.problem.steps) for r in reqs])
+        key = f"{arch}|serve|{sig}|{_library_stamp()}"
+        db = _load() if use_cache else {}
+        if use_cache and key in db:
+            out["schedules"][dtype] = tuple(db[key]["schedule"])
+            out["table"][dtype] = db[key]["table"]
+            block_votes.append(int(db[key]["block"]))
+            continue
+        tdt = torch.complex64 if dtype == "c64" else torch.complex128
+        plans, psis = [], []
+        for r in reqs:
+            p = r.problem
+            pl = Plan(p.nx, p.ny, p.dt, dtype, dx=p.dx, dy=p.dy, mass=p.mass, hbar=p.hbar,
+                      device=device)
+            pl.set_potential(wl.potential(p, device=device))
+            plans.append(pl)
+            psis.append(wl.initial_state(p, device=device, dtype=tdt))
+        rate: Dict[Tuple[Schedule, int], float] = {}
+        table: Dict[str, float] = {}
+        for cand in SERVE_CANDIDATES:
+            for block in SERVE_BLOCKS:
+                steps = [min(block, r.problem.steps) for r in reqs]
+                ms = time_block(plans, psis, steps, cand)
+                work = sum(r.problem.sites * n for r, n in zip(reqs, steps))
+                rate[(cand, block)] = work / (ms * 1e-3)
+                table[f"{','.join(map(str, cand))}|{block}"] = ms
+                if log:
+                    log(f"autotune serve {dtype} S={cand[0]} store={cand[3]} block={block}: "
+                        f"{ms:.2f} ms, {rate[(cand, block)]:.3e} site-steps/s")
+        best_sched = max(SERVE_CANDIDATES,
+                         key=lambda c: max(rate[(c, b)] for b in SERVE_BLOCKS))
+        top = max(rate[(best_sched, b)] for b in SERVE_BLOCKS)
+        block = min(b for b in SERVE_BLOCKS
+                    if rate[(best_sched, b)] >= top * (1.0 - SERVE_BLOCK_SLACK))
+        out["schedules"][dtype] = best_sched
+        out["table"][dtype] = table
+        block_votes.append(block)
+        if use_cache:
+            db[key] = {"schedule": list(best_sched), "block": block, "table": table}
+            _store(db)
+        del plans, psis
+    out["block_steps"] = max(block_votes) if block_votes else 20
+    return out

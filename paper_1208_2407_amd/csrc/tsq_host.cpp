@@ -70,10 +70,14 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 tsq::Coef64 block_coef(double tau, double J, double hbar) {
     const double al = tau * J / hbar;
     const double h = std::sin(0.5 * al);
-    return tsq::Coef64{std::sin(al), 2.0 * h * h};
+    return tsq::Coef64{std::sin(al), 2.0 * h * h, al};
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Largest rotation angle of a whole time step (|dt| J / hbar) a periodic 2D
+// plan accepts: tan of it stays below 1.6.
+constexpr double kMaxAngle = 1.0;
 
 constexpr size_t kScratchBytes = (2 * tsq::kReduceBlocks + 2) * sizeof(double);
 
@@ -140,7 +144,10 @@ int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl, bool lds,
         (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl, lds, closed, td) *
         tsq::kWavesPerBlock;
     const long long pairs = (p->p.ny + 1) / 2;
-    long long segs = slots / g.nstrips;
+    // a launch has one block per segment of kWavesPerBlock strips
+    const long long strip_slots =
+        (g.nstrips + tsq::kWavesPerBlock - 1) / tsq::kWavesPerBlock * tsq::kWavesPerBlock;
+    long long segs = slots / strip_slots;
     if (segs < 1) segs = 1;
     if (segs > pairs) segs = pairs;
     long long pairs_per_seg = (pairs + segs - 1) / segs;
@@ -297,14 +304,19 @@ void append_launch(tsq_batch* b, int steps, bool last, const std::vector<tsq::Pa
                    int slots) {
     const int ppl = b->sched.pairs_per_lane;
     const int K = steps + (last ? 1 : 0);
-    // Tile height: the strips of all problems stacked, cut into about one tile
-    // per resident wavefront, never shorter than 2K row pairs.
-    long long strip_rows = 0;
-    for (const tsq::PassDesc& d : descs)
-        strip_rows += (long long)tsq::march_geometry(d.nx, d.ny, steps, last, ppl, 2).nstrips * d.ny;
-    long long h = (strip_rows + slots - 1) / slots;
-    if (h < 4LL * K) h = 4LL * K;
-    h = (h + 1) & ~1LL;
+    // Tile height: the schedule's segment_rows if set; else the strips of all
+    // problems stacked, cut into about one tile per resident wavefront, never
+    // shorter than 2K row pairs.
+    long long h = b->sched.segment_rows;
+    if (h <= 0) {
+        long long strip_rows = 0;
+        for (const tsq::PassDesc& d : descs)
+            strip_rows +=
+                (long long)tsq::march_geometry(d.nx, d.ny, steps, last, ppl, 2).nstrips * d.ny;
+        h = (strip_rows + slots - 1) / slots;
+        if (h < 4LL * K) h = 4LL * K;
+        h = (h + 1) & ~1LL;
+    }
 
     std::vector<tsq::MarchArgs<R>> jobs;
     std::vector<tsq::BatchTile> tiles;
@@ -382,12 +394,11 @@ int tsq_batch_create(tsq_plan* const* plans, void* const* psi, void* const* ws, 
         if (reinterpret_cast<uintptr_t>(psi[i]) % 16 != 0)
             return fail(TSQ_ERR_ARG, "entry %d: psi must be 16-byte aligned", i);
     }
-    tsq_schedule want = schedule ? *schedule : tsq_schedule{0, 0, 0, 0};
-    want.segment_rows = 0;
+    const tsq_schedule want = schedule ? *schedule : tsq_schedule{0, 0, 0, 0};
     tsq_schedule sc;
     if (want.steps_per_pass < 0 || want.steps_per_pass > tsq::kMaxSteps || want.pairs_per_lane < 0 ||
         want.pairs_per_lane > 2 || want.phase_store < 0 || want.phase_store > 2 ||
-        !resolve_schedule(want, sc))
+        want.segment_rows < 0 || (want.segment_rows & 1) || !resolve_schedule(want, sc))
         return fail(TSQ_ERR_ARG, "invalid batch schedule");
     int cus = device_cus();
     if (cus <= 0) return fail(TSQ_ERR_DEVICE, "no device to size the batch for");
@@ -524,6 +535,34 @@ int tsq_batch_launch(tsq_batch* b, int32_t use_graph, void* stream) {
     return ok();
 }
 
+int tsq_batch_evolve_workspace_size(tsq_plan* const* plans, void* const* psi, void* const* ws,
+                                    const int64_t* steps, int32_t n, const tsq_schedule* schedule,
+                                    size_t* bytes) {
+    if (!bytes) return fail(TSQ_ERR_ARG, "null output pointer");
+    tsq_batch* b = nullptr;
+    int rc = tsq_batch_create(plans, psi, ws, steps, n, schedule, &b);
+    if (rc) return rc;
+    tsq_batch_workspace_size(b, bytes);
+    delete b;
+    return ok();
+}
+
+int tsq_batch_evolve(tsq_plan* const* plans, void* const* psi, void* const* ws, const int64_t* steps,
+                     int32_t n, const tsq_schedule* schedule, void* bws, size_t bws_bytes,
+                     void* stream) {
+    tsq_batch* b = nullptr;
+    int rc = tsq_batch_create(plans, psi, ws, steps, n, schedule, &b);
+    if (rc) return rc;
+    rc = tsq_batch_upload(b, bws, bws_bytes, stream);
+    if (!rc) rc = tsq_batch_launch(b, 0, stream);
+    // the upload reads pageable host memory, which the copy has staged by the
+    // time it returns; the host image is kept until the thread's next call anyway
+    thread_local std::vector<unsigned char> keep;
+    keep.swap(b->blob);
+    delete b;
+    return rc ? rc : ok();
+}
+
 const char* tsq_last_error(void) { return g_err.c_str(); }
 
 int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
@@ -595,6 +634,21 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
         u.ox2 = block_coef(dts[k], p->Jx, hb);
         u.oy2 = block_coef(dts[k], p->Jy, hb);
     }
+    // Periodic 2D meshes rotate in the tangent form (tan al of the half and
+    // whole time step), which needs every angle well inside (-pi/2, pi/2).
+    if (!three_d && pr->bc == TSQ_BC_PERIODIC) {
+        for (int k = 0; k < p->nkinds; ++k) {
+            const SubStep& u = p->kind[k];
+            if (std::fabs(u.ox2.al) >= kMaxAngle || std::fabs(u.oy2.al) >= kMaxAngle) {
+                delete p;
+                return fail(TSQ_ERR_UNSUPPORTED,
+                            "|dt| hbar / (2 m da^2) = %g rad per step along %s is too large for the "
+                            "tangent-form rotation of periodic meshes (limit %g)",
+                            std::max(std::fabs(u.ox2.al), std::fabs(u.oy2.al)),
+                            std::fabs(u.ox2.al) >= std::fabs(u.oy2.al) ? "x" : "y", kMaxAngle);
+            }
+        }
+    }
     p->oxh = p->kind[0].oxh;
     p->oyh = p->kind[0].oyh;
     p->ox2 = p->kind[0].ox2;
@@ -602,7 +656,10 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
     resolve_schedule(tsq_schedule{0, 0, 0, 0}, p->sched);
     p->sites = (size_t)pr->nx * (size_t)pr->ny * (size_t)p->p.nz;
     p->elem = pr->dtype == TSQ_C128 ? 16 : 8;
-    p->pelem = 16;  // complex128: exp(-i phi); complex64: hi + lo complex floats
+    // bytes per site of a phase-table area: complex128 exp(-i phi) (16);
+    // complex64 uses 8 (two 32-bit fixed-point parts) and the time-dependent
+    // table of either dtype 16, so the area keeps 16
+    p->pelem = 16;
     p->off_psi2 = 0;
     p->off_ptab = align_up(p->sites * p->elem, 256);
     size_t end = p->off_ptab;

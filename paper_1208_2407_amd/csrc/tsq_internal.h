@@ -2,15 +2,19 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stddef.h>
+
+#include <cmath>
 #include <stdint.h>
 
 namespace tsq {
 
 // Coefficients of one 2x2 block exponential [[c, i s], [i s, c]], held as
-// s = sin(al) and d = 1 - c = 2 sin^2(al/2).
+// s = sin(al) and d = 1 - c = 2 sin^2(al/2), and its angle al.
 struct Coef64 {
     double s, d;
+    double al;
 };
 
 // Launch description of one fused pass of `steps` time steps over the mesh.
@@ -53,6 +57,21 @@ MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per
 // Kernel arguments of one pass over one problem (also the job record of the
 // batched kernel, uploaded to device memory).  R = double (complex128) or
 // float (complex64).
+//
+// Two forms of the rotations.  Closed meshes apply every block exponential
+// in the delta form a' = a + (i s b - d a) (4 multiply-adds per site).
+// Periodic meshes use the tangent form: the even factors and the odd y
+// factor of a step rotate as (a, b) <- (a + i t b, b + i t a), t = tan(al),
+// which is sec(al) times the block exponential (2 multiply-adds per site);
+// every site of a periodic mesh meets exactly one odd x pair per step, so the
+// odd x factor, in the delta form, carries the product of the step's cos(al)
+// factors as well (its coefficients s' = m sin(al_x), d' = 1 - m cos(al_x),
+// with m the inverse product of the tangent factors' moduli, computed from
+// the rounded tangents so each step stays unitary up to the rounding of s'
+// and d').  Field use:            delta form        tangent form
+//   o1x*/o2x*/c1x*  (s, d)         odd x             odd x, scale included
+//   o1y*/o2y*/c1y*  (s, d) / t     odd y (s, d)      odd y: t in *ys
+//   eh*             (s, d) / t     even x, y         t in ehxs, ehys
 template <class R>
 struct MarchArgs {
     const void* src;
@@ -61,9 +80,30 @@ struct MarchArgs {
     int nx, ny, strip_sites, seg_rows, nstrips, nsegs;
     R o1xs, o1xd, o1ys, o1yd;  // odd factors opening the pass: tau = dt/2 (first pass) or dt
     R o2xs, o2xd, o2ys, o2yd;  // odd factors between steps, tau = dt
-    R ehxs, ehxd, ehys, ehyd;  // even factors and the closing odd factors, tau = dt/2
+    R ehxs, ehxd, ehys, ehyd;  // even factors, tau = dt/2
+    R c1xs, c1xd, c1ys, c1yd;  // odd factors closing the evolution, tau = dt/2
     double g[kMaxSteps];       // time-dependent potential: f_n of step k of the pass
 };
+
+// Tangent-form coefficients (periodic meshes), rounded to R.  `ox`, `oy`: the
+// odd factors of the stage; `with_even`: the stage also applies the four even
+// half factors (every stage but the closing one).
+template <class R>
+void tangent_stage(const Coef64& ox, const Coef64& oy, const PassDesc& d, bool with_even, R& xs,
+                   R& xd, R& yt) {
+    yt = (R)std::tan(oy.al);
+    // log of the squared modulus the tangent factors multiply every site by:
+    // log(1 + t^2) per factor, from the rounded tangents
+    const auto lg = [](R t) { return std::log1p((double)t * (double)t); };
+    double L = lg(yt);
+    if (with_even) L += 2.0 * lg((R)std::tan(d.oxh.al)) + 2.0 * lg((R)std::tan(d.oyh.al));
+    // odd x: modulus m = exp(-L/2), angle ox.al; 1 - d' = sqrt(m^2 - s'^2)
+    const double m2 = std::exp(-L);
+    xs = (R)(std::sqrt(m2) * std::sin(ox.al));
+    const double s2 = (double)xs * (double)xs;
+    const double one_minus_x = -std::expm1(-L) + s2;  // 1 - (m^2 - s'^2)
+    xd = (R)(one_minus_x / (1.0 + std::sqrt(m2 - s2)));
+}
 
 template <class R>
 MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
@@ -79,9 +119,19 @@ MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
     a.nsegs = g.nsegs;
     const Coef64& ox1 = d.first ? d.oxh : d.ox2;
     const Coef64& oy1 = d.first ? d.oyh : d.oy2;
-    a.o1xs = (R)ox1.s; a.o1xd = (R)ox1.d; a.o1ys = (R)oy1.s; a.o1yd = (R)oy1.d;
-    a.o2xs = (R)d.ox2.s; a.o2xd = (R)d.ox2.d; a.o2ys = (R)d.oy2.s; a.o2yd = (R)d.oy2.d;
-    a.ehxs = (R)d.oxh.s; a.ehxd = (R)d.oxh.d; a.ehys = (R)d.oyh.s; a.ehyd = (R)d.oyh.d;
+    if (d.closed) {
+        a.o1xs = (R)ox1.s; a.o1xd = (R)ox1.d; a.o1ys = (R)oy1.s; a.o1yd = (R)oy1.d;
+        a.o2xs = (R)d.ox2.s; a.o2xd = (R)d.ox2.d; a.o2ys = (R)d.oy2.s; a.o2yd = (R)d.oy2.d;
+        a.ehxs = (R)d.oxh.s; a.ehxd = (R)d.oxh.d; a.ehys = (R)d.oyh.s; a.ehyd = (R)d.oyh.d;
+        a.c1xs = a.ehxs; a.c1xd = a.ehxd; a.c1ys = a.ehys; a.c1yd = a.ehyd;
+    } else {
+        tangent_stage<R>(ox1, oy1, d, true, a.o1xs, a.o1xd, a.o1ys);
+        tangent_stage<R>(d.ox2, d.oy2, d, true, a.o2xs, a.o2xd, a.o2ys);
+        tangent_stage<R>(d.oxh, d.oyh, d, false, a.c1xs, a.c1xd, a.c1ys);
+        a.ehxs = (R)std::tan(d.oxh.al);
+        a.ehys = (R)std::tan(d.oyh.al);
+        a.o1yd = a.o2yd = a.c1yd = a.ehxd = a.ehyd = R(0);
+    }
     for (int k = 0; k < kMaxSteps; ++k) a.g[k] = (d.td && d.f && k < d.steps) ? d.f[k] : 0.0;
     return a;
 }

@@ -1,7 +1,8 @@
 // HIP kernels for gfx950 of the second-order Trotter-Suzuki step
-// (Wittek & Cucchietti, Sec. 2): phase-table setup (row a0), the FP64
-// norm/energy reductions (row a7), and the launchers of the fused step march
-// whose templates live in tsq_march.hpp (rows a1-a6).
+// (Wittek & Cucchietti, Sec. 2): the phase table of the diagonal part H0, the
+// FP64 norm and energy of the mesh Hamiltonian, and the launchers of the fused
+// step march (the product U2 of Eq. "secondorder") whose templates live in
+// tsq_march.hpp.
 
 #include <utility>
 
@@ -53,7 +54,7 @@ Variant variant_of(bool batch, bool closed, bool td) {
     return closed ? Variant::Closed : Variant::Single;
 }
 
-// ------------------------------------------------------------------ phase table (row a0)
+// ------------------------------------------------------------------ phase table of H0 (Sec. 2)
 
 __global__ void phase_table_c128(const double* __restrict__ V, double2* __restrict__ P,
                                  long long n, double dt, double eps0, double hbar) {
@@ -66,16 +67,16 @@ __global__ void phase_table_c128(const double* __restrict__ V, double2* __restri
     }
 }
 
-__global__ void phase_table_c64(const double* __restrict__ V, float4* __restrict__ P,
+// complex64: cos(phi) and -sin(phi) as 32-bit fixed point, value * 2^30
+// rounded to nearest (|value| <= 1, so 2^30 fits; error <= 2^-31 per part).
+__global__ void phase_table_c64(const double* __restrict__ V, int2* __restrict__ P,
                                 long long n, double dt, double eps0, double hbar) {
     for (long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x; l < n;
          l += (long long)gridDim.x * blockDim.x) {
         double phi = dt * (V[l] + eps0) / hbar;
         double s, c;
         sincos(phi, &s, &c);
-        float hr = (float)c, hi = (float)(-s);
-        float lr = (float)(c - (double)hr), li = (float)(-s - (double)hi);
-        P[l] = make_float4(hr, hi, lr, li);
+        P[l] = make_int2(__double2int_rn(c * 0x1p30), __double2int_rn(-s * 0x1p30));
     }
 }
 
@@ -89,7 +90,7 @@ __global__ void td_table(const double* __restrict__ V0, const double* __restrict
         T[l] = make_double2(dt * (V0[l] + eps0) / hbar, dt * W[l] / hbar);
 }
 
-// ------------------------------------------------------------------ observables (row a7)
+// ------------------------------------------------------------------ norm and energy (Sec. 2)
 
 __device__ __forceinline__ void load_site(const void* psi, long long l, double& re, double& im, C128) {
     double2 v = reinterpret_cast<const double2*>(psi)[l];
@@ -193,7 +194,8 @@ MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per
     g.nstrips = (nx + g.strip_sites - 1) / g.strip_sites;
     g.nsegs = (ny + seg_rows - 1) / seg_rows;
     g.tiles = (long long)g.nstrips * g.nsegs;
-    g.blocks = (int)((g.tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    // one block per segment of kWavesPerBlock neighbouring strips
+    g.blocks = (int)((long long)((g.nstrips + kWavesPerBlock - 1) / kWavesPerBlock) * g.nsegs);
     return g;
 }
 
@@ -207,7 +209,7 @@ hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long 
                            reinterpret_cast<double2*>(ptab), sites, dt, eps0, hbar);
     else
         hipLaunchKernelGGL(phase_table_c64, dim3(blocks), dim3(threads), 0, s, V,
-                           reinterpret_cast<float4*>(ptab), sites, dt, eps0, hbar);
+                           reinterpret_cast<int2*>(ptab), sites, dt, eps0, hbar);
     return hipGetLastError();
 }
 

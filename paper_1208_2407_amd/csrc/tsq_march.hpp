@@ -75,6 +75,18 @@ __device__ __forceinline__ void rot_pair(R& ar, R& ai, R& br, R& bi, R s, R d) {
     rot_site(br, bi, a0, a1, s, d);
 }
 
+// Tangent form of a pair rotation: (a, b) <- (a + i t b, b + i t a), which is
+// sec(al) times the block exponential for t = tan(al); the cos(al) factors it
+// leaves out are applied by the odd x factor of the same step.
+template <class R>
+__device__ __forceinline__ void rot_pair_t(R& ar, R& ai, R& br, R& bi, R t) {
+    const R a0 = ar, a1 = ai;
+    ar = mad(-t, bi, ar);
+    ai = mad(t, br, ai);
+    br = mad(-t, a1, br);
+    bi = mad(t, a0, bi);
+}
+
 // Potential phase, complex128: psi <- psi * p, p = exp(-i phi) in FP64.
 __device__ __forceinline__ void apply_phase(double& re, double& im, const double2 p) {
     double t = im * p.y;
@@ -85,8 +97,9 @@ __device__ __forceinline__ void apply_phase(double& re, double& im, const double
 }
 
 // Potential phase, complex64: p = (hi.re, hi.im, lo.re, lo.im) with
-// exp(-i phi) = hi + lo to ~48 bits; the lo product is formed first so the
-// table contributes no coherent per-site error step after step.
+// hi + lo the table's 31-bit value of exp(-i phi); the lo product is formed
+// first so the table's rounding to complex64 adds no coherent per-site error
+// step after step.
 __device__ __forceinline__ void apply_phase(float& re, float& im, const float4 p) {
     float tr = mad(re, p.z, -(im * p.w));
     float ti = mad(re, p.w, im * p.z);
@@ -175,14 +188,33 @@ __device__ __forceinline__ void apply_phase_td(float& re, float& im, const doubl
 
 // ------------------------------------------------------------------ dtype traits
 
+// R: the real type of psi.  PT: a phase factor as the march holds it in
+// registers.  TT: a phase factor as the table stores it in device memory.
 struct C128 {
     using R = double;
     using PT = double2;
+    using TT = double2;
 };
 struct C64 {
     using R = float;
     using PT = float4;
+    using TT = int2;
 };
+
+// Phase table entry -> phase factor.  complex128: exp(-i phi) as is.
+// complex64: the table holds cos(phi) and -sin(phi) as 32-bit fixed-point
+// numbers (scale 2^30; 8 bytes, the size of a complex64, but about 31 bits
+// per part instead of 24, so the coherent per-site error of a rounded table,
+// repeated every step, stays below 7e-10 per step); they split exactly into a
+// hi float (the top 24 bits) and a lo float (the low 7 bits), the pair the
+// complex64 phase multiply takes.
+__device__ __forceinline__ double2 decode_phase(double2 t) { return t; }
+__device__ __forceinline__ float4 decode_phase(int2 t) {
+    const float sc = 0x1p-30f;
+    const int hx = t.x & ~0x7f, hy = t.y & ~0x7f;
+    return make_float4((float)hx * sc, (float)hy * sc, (float)(t.x - hx) * sc,
+                       (float)(t.y - hy) * sc);
+}
 
 template <class R, int SPL>
 struct Row {
@@ -289,6 +321,20 @@ __device__ __forceinline__ void pair_y(Row<R, SPL>& u, Row<R, SPL>& v, R s, R d)
     for (int i = 0; i < SPL; ++i) rot_pair(u.re[i], u.im[i], v.re[i], v.im[i], s, d);
 }
 
+// The same in the tangent form (periodic meshes).
+template <class R, int SPL>
+__device__ __forceinline__ void pair_y_t(Row<R, SPL>& u, Row<R, SPL>& v, R t) {
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) rot_pair_t(u.re[i], u.im[i], v.re[i], v.im[i], t);
+}
+
+// Even x-pairs in the tangent form (periodic meshes: every pair exists).
+template <class R, int SPL>
+__device__ __forceinline__ void even_x_t(Row<R, SPL>& w, R t) {
+#pragma unroll
+    for (int p = 0; p < SPL / 2; ++p) rot_pair_t(w.re[2 * p], w.im[2 * p], w.re[2 * p + 1], w.im[2 * p + 1], t);
+}
+
 template <class PT, class R, int SPL>
 __device__ __forceinline__ void phase_row(Row<R, SPL>& w, const PT* p) {
 #pragma unroll
@@ -354,7 +400,9 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // potential (TD) the phase pair holds (theta0, w) per site and stage k forms
 // step k's factor from a.g[k].  Closed meshes rotate the y-pairs that cross
 // a wall with zero coefficients (`qk` is the pair stage k completes; a
-// wavefront-uniform test).
+// wavefront-uniform test) and apply every factor in the delta form; periodic
+// meshes apply the even and odd y factors in the tangent form and the odd x
+// factor, which every site meets once per stage, with the stage's cosines.
 template <int S, int K, bool CLOSED, bool TD, class R, int SPL, class PT, class PhaseFn>
 __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
                                                const MarchArgs<R>& a,
@@ -366,7 +414,30 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
     } else if (k < S) {
         oxs = a.o2xs; oxd = a.o2xd; oys = a.o2ys; oyd = a.o2yd;
     } else {
-        oxs = a.ehxs; oxd = a.ehxd; oys = a.ehys; oyd = a.ehyd;
+        oxs = a.c1xs; oxd = a.c1xd; oys = a.c1ys; oyd = a.c1yd;
+    }
+    if constexpr (!CLOSED) {
+        (void)oyd; (void)qk; (void)rev;
+        odd_x<false>(o.g, oxs, oxd, xm);
+        odd_x<false>(n.f, oxs, oxd, xm);
+        pair_y_t(o.g, n.f, oys);
+        if (k < S) {
+            const PhasePair<PT, SPL> ph = phase(k);
+            even_x_t(o.f, a.ehxs);
+            even_x_t(o.g, a.ehxs);
+            pair_y_t(o.f, o.g, a.ehys);
+            if constexpr (TD) {
+                phase_row_td(o.f, ph.f, a.g[k]);
+                phase_row_td(o.g, ph.g, a.g[k]);
+            } else {
+                phase_row(o.f, ph.f);
+                phase_row(o.g, ph.g);
+            }
+            pair_y_t(o.f, o.g, a.ehys);
+            even_x_t(o.f, a.ehxs);
+            even_x_t(o.g, a.ehxs);
+        }
+        return;
     }
     // odd y-pair: rows (2qk+1, 2qk+2) marching down, (2qk-1, 2qk) marching up
     const bool oy_ok = !CLOSED || (rev ? (qk >= 1 && 2 * qk < a.ny) : (qk >= 0 && 2 * qk + 2 < a.ny));
@@ -453,6 +524,8 @@ __device__ __forceinline__ PT zero_phase() {
 // j-1's phase to the ring at the end of iteration j.
 template <class T, bool TD>
 using PhaseT = std::conditional_t<TD, double2, typename T::PT>;
+template <class T, bool TD>
+using TableT = std::conditional_t<TD, double2, typename T::TT>;
 
 template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD>
 __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, int strip, int seg,
@@ -546,17 +619,17 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         step_row(rpsi);
     };
     auto load_phase_row = [&](int r, PT (&v)[SPL]) {
-        const PT* P = reinterpret_cast<const PT*>(a.ptab);
+        const TableT<T, TD>* P = reinterpret_cast<const TableT<T, TD>*>(a.ptab);
         if constexpr (CLOSED) {
             const long long off = (long long)clamp_row(r) * nx;
 #pragma unroll
-            for (int i = 0; i < SPL; ++i) v[i] = P[off + ccol[i]];
+            for (int i = 0; i < SPL; ++i) v[i] = decode_phase(P[off + ccol[i]]);
         } else {
             const long long off = (long long)r * nx;
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
-                v[2 * p] = P[off + col[p]];
-                v[2 * p + 1] = P[off + col[p] + 1];
+                v[2 * p] = decode_phase(P[off + col[p]]);
+                v[2 * p + 1] = decode_phase(P[off + col[p] + 1]);
             }
         }
     };
@@ -675,15 +748,21 @@ march_kernel(const MarchArgs<typename T::R> a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
     // XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
     // block b runs on XCD b % 8; give each XCD a contiguous run of tiles so
-    // the halo rows shared by neighbouring segments meet in one L2.
+    // the halo rows shared by neighbouring segments meet in one L2.  A block
+    // marches one segment of kWavesPerBlock neighbouring strips (one per
+    // wavefront): the halo columns two strips share are read by two
+    // wavefronts of one compute unit at about the same time, so the second
+    // read hits the cache.
     const int nb = gridDim.x;
     const int full = nb & ~7;
     const int b = blockIdx.x;
     const int lb = (b < full) ? ((b & 7) * (full >> 3) + (b >> 3)) : b;
-    const long long tile = (long long)lb * kWavesPerBlock + wave;
-    if (tile >= (long long)a.nstrips * a.nsegs) return;  // uniform per wavefront
-    const int strip = (int)(tile / a.nsegs);
-    const int seg = (int)(tile - (long long)strip * a.nsegs);
+    const int ngroups = (a.nstrips + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (lb >= ngroups * a.nsegs) return;  // uniform per block
+    const int grp = lb / a.nsegs;
+    const int seg = lb - grp * a.nsegs;
+    const int strip = grp * kWavesPerBlock + wave;
+    if (strip >= a.nstrips) return;  // uniform per wavefront
     march_tile<T, S, LAST, PPL, LDS, CLOSED, TD>(a, strip, seg, seg & 1, lane,
                                                  &rings[LDS ? wave : 0].v[0][0][0][lane]);
 }

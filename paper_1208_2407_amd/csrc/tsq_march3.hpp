@@ -1,6 +1,8 @@
-// Three-dimensional march: the second-order step on a (nz, ny, nx) mesh, the
-// seven-part split that the paper names as its extension to three
-// dimensions (Sec. 5), one time step per pass.  Per step, first factor first:
+// Three-dimensional march: the second-order step on a (nz, ny, nx) mesh, one
+// time step per pass.  Sec. 2 splits the 2D mesh Hamiltonian into five parts
+// (the diagonal and the even and odd pairs of each axis); this march extends
+// that split to three axes, seven parts (Sec. 5 names three dimensions as
+// future work).  Per step, first factor first:
 //   Ox Oy Oz Ex Ey Ez P Ez Ey Ex Oz Oy Ox   (kinetic factors for dt/2)
 // with consecutive steps sharing their odd factors as in the 2D march; a
 // closing pass after the last step applies its final Oz Oy Ox.
@@ -213,11 +215,11 @@ __device__ __forceinline__ void march3_tile(const March3Args<typename T::R>& a, 
         step_z(rz);
     };
     auto load_phase_plane = [&](int z, PT (&v)[2][2]) {
-        const PT* P = reinterpret_cast<const PT*>(a.ptab);
-        v[0][0] = P[z * plane + rowa];
-        v[0][1] = P[z * plane + rowa + 1];
-        v[1][0] = P[z * plane + rowb];
-        v[1][1] = P[z * plane + rowb + 1];
+        const typename T::TT* P = reinterpret_cast<const typename T::TT*>(a.ptab);
+        v[0][0] = decode_phase(P[z * plane + rowa]);
+        v[0][1] = decode_phase(P[z * plane + rowa + 1]);
+        v[1][0] = decode_phase(P[z * plane + rowb]);
+        v[1][1] = decode_phase(P[z * plane + rowb + 1]);
     };
     auto load_phase = [&](PlanePhase<PT>& ph) {
         load_phase_plane(rzp + fo, ph.f);

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_abi_version():
-    assert tsq.tsq_abi_version() == 4
+    assert tsq.tsq_abi_version() == 5
 
 
 def problem(**kw):
@@ -53,6 +53,9 @@ def problem(**kw):
     (dict(nz=3), -2), (dict(nz=-1), -2), (dict(nz=4, dz=0.0), -1),
     (dict(nz=4, bc=1), -7), (dict(nz=4, order=4), -7),
     (dict(nx=2048, ny=2048, nz=1024), -2),
+    # periodic 2D meshes rotate in the tangent form: |dt| hbar / (2 m da^2) < 1 rad
+    (dict(dt=2.0), -7), (dict(dt=-2.0), -7), (dict(dt=0.3, dy=0.3), -7),
+    (dict(dt=3.2, order=4), -7),   # its longest sub-step, |1-4p| dt, is 1.05 rad
 ])
 def test_plan_create_rejects(kw, status):
     with pytest.raises(tsq.TsqError) as ei:
@@ -71,6 +74,14 @@ def test_plan_create_accepts_negative_dt_and_reports_workspace():
             assert tsq.tsq_last_error() == ""
         finally:
             tsq.tsq_plan_destroy(h)
+
+
+def test_large_steps_stay_allowed_where_no_tangent_form_runs():
+    # closed meshes and 3D meshes rotate in the delta form: any finite dt
+    # order 4: the longest sub-step is |1-4p| dt = 0.66 dt
+    for kw in (dict(dt=2.0, bc=1), dict(dt=2.0, nz=4), dict(dt=1.99), dict(dt=2.5, order=4)):
+        h = tsq.tsq_plan_create(problem(**kw))
+        tsq.tsq_plan_destroy(h)
 
 
 def sched(*v):
