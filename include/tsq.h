@@ -286,6 +286,19 @@ int tsq_batch_evolve(tsq_plan* const* plans, void* const* psi_dev, void* const* 
                      const int64_t* steps, int32_t n, const tsq_schedule* schedule, void* bws,
                      size_t bws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * as tsq_batch_evolve, with the work lists in a device array the library holds
+ * (16 MiB per GPU, kept until the process ends) instead of a caller buffer.
+ * Allocates nothing.  Calls on one GPU share that array: calls that overlap
+ * on one GPU (different streams, or host threads) race; calls in one stream
+ * are ordered.  Errors: those of tsq_batch_evolve; TSQ_ERR_WORKSPACE when the
+ * work lists (tsq_batch_evolve_workspace_size) exceed 16 MiB;
+ * TSQ_ERR_DEVICE if the array's address cannot be found. */
+int tsq_batch_evolve_noalloc(tsq_plan* const* plans, void* const* psi_dev, void* const* ws,
+                             const int64_t* steps, int32_t n, const tsq_schedule* schedule,
+                             void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,7 +33,7 @@ EXPORTED = ("tsq_abi_version", "tsq_last_error", "tsq_plan_create", "tsq_plan_de
             "tsq_evolve_td", "tsq_observables",
             "tsq_batch_create", "tsq_batch_destroy", "tsq_batch_workspace_size", "tsq_batch_info",
             "tsq_batch_upload", "tsq_batch_launch", "tsq_batch_evolve_workspace_size",
-            "tsq_batch_evolve")
+            "tsq_batch_evolve", "tsq_batch_evolve_noalloc")
 
 
 class TsqError(RuntimeError):
@@ -107,6 +107,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
                                                     ctypes.POINTER(sz)]
     lib.tsq_batch_evolve.argtypes = [vpp, vpp, vpp, ctypes.POINTER(i64), i32,
                                      ctypes.POINTER(tsq_schedule), vp, sz, vp]
+    lib.tsq_batch_evolve_noalloc.argtypes = [vpp, vpp, vpp, ctypes.POINTER(i64), i32,
+                                             ctypes.POINTER(tsq_schedule), vp]
     for name in EXPORTED[2:]:
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
@@ -247,6 +249,13 @@ def tsq_batch_evolve(plans, psi_devs, wss, steps, schedule: Optional[tsq_schedul
     _check(load_library().tsq_batch_evolve(
         a, b, c, st, n, ctypes.byref(schedule) if schedule is not None else None, bws, bws_bytes,
         stream))
+
+
+def tsq_batch_evolve_noalloc(plans, psi_devs, wss, steps, schedule: Optional[tsq_schedule],
+                             stream: int) -> None:
+    a, b, c, st, n = _batch_args(plans, psi_devs, wss, steps)
+    _check(load_library().tsq_batch_evolve_noalloc(
+        a, b, c, st, n, ctypes.byref(schedule) if schedule is not None else None, stream))
 
 
 # ---------------------------------------------------------------- convenience layer

@@ -550,9 +550,31 @@ int tsq_batch_evolve_workspace_size(tsq_plan* const* plans, void* const* psi, vo
 int tsq_batch_evolve(tsq_plan* const* plans, void* const* psi, void* const* ws, const int64_t* steps,
                      int32_t n, const tsq_schedule* schedule, void* bws, size_t bws_bytes,
                      void* stream) {
+    return tsq::batch_evolve_into(plans, psi, ws, steps, n, schedule, bws, bws_bytes, stream,
+                                  nullptr);
+}
+
+const char* tsq_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+int tsq::set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int tsq::batch_evolve_into(tsq_plan* const* plans, void* const* psi, void* const* ws,
+                           const int64_t* steps, int32_t n, const tsq_schedule* schedule,
+                           void* bws, size_t bws_bytes, void* stream, size_t* need) {
     tsq_batch* b = nullptr;
     int rc = tsq_batch_create(plans, psi, ws, steps, n, schedule, &b);
     if (rc) return rc;
+    if (need) tsq_batch_workspace_size(b, need);
     rc = tsq_batch_upload(b, bws, bws_bytes, stream);
     if (!rc) rc = tsq_batch_launch(b, 0, stream);
     // the upload reads pageable host memory, which the copy has staged by the
@@ -563,7 +585,7 @@ int tsq_batch_evolve(tsq_plan* const* plans, void* const* psi, void* const* ws, 
     return rc ? rc : ok();
 }
 
-const char* tsq_last_error(void) { return g_err.c_str(); }
+extern "C" {
 
 int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
     if (pr == nullptr || out == nullptr) return fail(TSQ_ERR_ARG, "null problem or output pointer");

@@ -8,6 +8,8 @@
 #include <cmath>
 #include <stdint.h>
 
+#include "../../include/tsq.h"
+
 namespace tsq {
 
 // Coefficients of one 2x2 block exponential [[c, i s], [i s, c]], held as
@@ -174,6 +176,20 @@ hipError_t launch_observables(int dtype, const void* psi, const double* V, int n
                               int nblocks, double* result, hipStream_t s);
 
 constexpr int kReduceBlocks = 1024;
+
+// Bytes of the library-held device array of tsq_batch_evolve_noalloc (per GPU).
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+
+// Record `fmt` as the calling thread's last error and return `code`.
+int set_error(int code, const char* fmt, ...);
+
+// Build the batch of tsq_batch_create, copy its work lists to `bws` (at most
+// `bws_bytes`) and enqueue every pass on `stream`; `need` (if not null)
+// receives the work lists' size in bytes.  Shared by tsq_batch_evolve and its
+// workspace-free variant.
+int batch_evolve_into(tsq_plan* const* plans, void* const* psi, void* const* ws,
+                      const int64_t* steps, int32_t n, const tsq_schedule* schedule, void* bws,
+                      size_t bws_bytes, void* stream, size_t* need);
 constexpr int kReduceThreads = 256;
 
 }  // namespace tsq
