@@ -767,9 +767,18 @@ int tsq_set_potential(tsq_plan* plan, const double* V, void* ws, size_t ws_bytes
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
     for (int k = 0; k < plan->nkinds; ++k) {
-        hipError_t e = tsq::launch_phase_table(plan->p.dtype, V, w + plan->kind[k].off_ptab,
-                                               (long long)plan->sites, plan->kind[k].dt,
-                                               plan->eps0, plan->p.hbar,
+        const SubStep& u = plan->kind[k];
+        // periodic 2D meshes: the table carries a step's cosines (the march's
+        // tangent-form factors leave them out), from the tangents as rounded
+        // in the plan's dtype
+        double scale = 1.0;
+        if (!plan->three_d && plan->p.bc == TSQ_BC_PERIODIC)
+            scale = std::exp(-0.5 * (plan->p.dtype == TSQ_C128
+                                         ? tsq::step_log_sec2<double>(u.oxh, u.oyh, u.ox2, u.oy2)
+                                         : tsq::step_log_sec2<float>(u.oxh, u.oyh, u.ox2, u.oy2)));
+        hipError_t e = tsq::launch_phase_table(plan->p.dtype, V, w + u.off_ptab,
+                                               (long long)plan->sites, u.dt, plan->eps0,
+                                               plan->p.hbar, scale,
                                                static_cast<hipStream_t>(stream));
         if (e != hipSuccess)
             return fail(TSQ_ERR_DEVICE, "phase table launch: %s", hipGetErrorString(e));
@@ -955,7 +964,9 @@ int tsq_observables(const tsq_plan* plan, const void* psi, const double* V, doub
     double* scratch = reinterpret_cast<double*>(static_cast<char*>(ws) + plan->off_scratch);
     double* result = scratch + 2 * tsq::kReduceBlocks;
     const long long rows = (long long)plan->p.ny * plan->p.nz;
-    const int nblocks = rows < tsq::kReduceBlocks ? (int)rows : tsq::kReduceBlocks;
+    // 3D: blocks over rows; 2D: the launcher cuts the mesh into at most this many items
+    const int nblocks = plan->three_d ? (rows < tsq::kReduceBlocks ? (int)rows : tsq::kReduceBlocks)
+                                      : tsq::kReduceBlocks;
     hipError_t e = plan->three_d
                        ? tsq::launch_observables3(plan->p.dtype, psi, V, plan->p.nx, plan->p.ny,
                                                   plan->p.nz, plan->Jx, plan->Jy, plan->Jz,

@@ -62,18 +62,26 @@ MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per
 //
 // Two forms of the rotations.  Closed meshes apply every block exponential
 // in the delta form a' = a + (i s b - d a) (4 multiply-adds per site).
-// Periodic meshes use the tangent form: the even factors and the odd y
-// factor of a step rotate as (a, b) <- (a + i t b, b + i t a), t = tan(al),
-// which is sec(al) times the block exponential (2 multiply-adds per site);
-// every site of a periodic mesh meets exactly one odd x pair per step, so the
-// odd x factor, in the delta form, carries the product of the step's cos(al)
-// factors as well (its coefficients s' = m sin(al_x), d' = 1 - m cos(al_x),
-// with m the inverse product of the tangent factors' moduli, computed from
-// the rounded tangents so each step stays unitary up to the rounding of s'
-// and d').  Field use:            delta form        tangent form
-//   o1x*/o2x*/c1x*  (s, d)         odd x             odd x, scale included
-//   o1y*/o2y*/c1y*  (s, d) / t     odd y (s, d)      odd y: t in *ys
-//   eh*             (s, d) / t     even x, y         t in ehxs, ehys
+// Periodic meshes use the tangent form (a, b) <- (a + i t b, b + i t a),
+// t = tan(al), which is sec(al) times the block exponential (2 multiply-adds
+// per site); every site of a periodic mesh meets each of a step's factors, so
+// the dropped cosines multiply every site alike and are restored elsewhere:
+//   * time-independent potentials: the phase table holds exp(-i phi) times the
+//     product g of a whole step's cosines (see phase_scale); stage 0 of a pass
+//     applies its odd x factor in the delta form with s' = t, d' = 0 (the
+//     tangent form, to the bit) or, in the first pass, with the coefficients of
+//     the opening half factor and the ratio of its cosines to those of g; the
+//     closing stage's odd x factor carries its own cosines;
+//   * time-dependent potentials (the phase formed in the march): every stage's
+//     odd x factor carries that stage's cosines.
+// Coefficients s' = m sin(al_x), d' = 1 - m cos(al_x) of an odd x factor in
+// the delta form with modulus m come from the rounded tangents, so every step
+// is unitary up to the rounding of s', d' and the table.  Field use
+// (periodic):
+//   o1x* (s', d')  stage 0 odd x         o1ys  stage 0 odd y tangent
+//   o2xs tangent / (s', d') (td)         o2ys  odd y tangent
+//   c1x* (s', d')  closing odd x         c1ys  closing odd y tangent
+//   ehxs, ehys     even tangents
 template <class R>
 struct MarchArgs {
     const void* src;
@@ -87,24 +95,34 @@ struct MarchArgs {
     double g[kMaxSteps];       // time-dependent potential: f_n of step k of the pass
 };
 
-// Tangent-form coefficients (periodic meshes), rounded to R.  `ox`, `oy`: the
-// odd factors of the stage; `with_even`: the stage also applies the four even
-// half factors (every stage but the closing one).
+// Tangent-form coefficients (periodic meshes), rounded to R.
 template <class R>
-void tangent_stage(const Coef64& ox, const Coef64& oy, const PassDesc& d, bool with_even, R& xs,
-                   R& xd, R& yt) {
-    yt = (R)std::tan(oy.al);
-    // log of the squared modulus the tangent factors multiply every site by:
-    // log(1 + t^2) per factor, from the rounded tangents
-    const auto lg = [](R t) { return std::log1p((double)t * (double)t); };
-    double L = lg(yt);
-    if (with_even) L += 2.0 * lg((R)std::tan(d.oxh.al)) + 2.0 * lg((R)std::tan(d.oyh.al));
-    // odd x: modulus m = exp(-L/2), angle ox.al; 1 - d' = sqrt(m^2 - s'^2)
+R tangent(const Coef64& c) {
+    return (R)std::tan(c.al);
+}
+// log(1 + t^2): log of the squared modulus a tangent factor multiplies by
+template <class R>
+double log_sec2(R t) {
+    return std::log1p((double)t * (double)t);
+}
+// Odd x factor in the delta form, angle al, squared modulus exp(-L):
+// s' = m sin(al), 1 - d' = sqrt(m^2 - s'^2) with s' rounded first.
+template <class R>
+void delta_odd_x(double al, double L, R& xs, R& xd) {
     const double m2 = std::exp(-L);
-    xs = (R)(std::sqrt(m2) * std::sin(ox.al));
+    xs = (R)(std::sqrt(m2) * std::sin(al));
     const double s2 = (double)xs * (double)xs;
     const double one_minus_x = -std::expm1(-L) + s2;  // 1 - (m^2 - s'^2)
     xd = (R)(one_minus_x / (1.0 + std::sqrt(m2 - s2)));
+}
+// Log of the squared modulus a steady step's tangent factors multiply every
+// site by (odd x and y at tau = dt, two even x and two even y at dt/2); the
+// phase table of a periodic mesh holds exp(-i phi) * exp(-L/2).
+template <class R>
+double step_log_sec2(const Coef64& oxh, const Coef64& oyh, const Coef64& ox2,
+                     const Coef64& oy2) {
+    return log_sec2(tangent<R>(ox2)) + log_sec2(tangent<R>(oy2)) +
+           2.0 * log_sec2(tangent<R>(oxh)) + 2.0 * log_sec2(tangent<R>(oyh));
 }
 
 template <class R>
@@ -127,12 +145,33 @@ MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
         a.ehxs = (R)d.oxh.s; a.ehxd = (R)d.oxh.d; a.ehys = (R)d.oyh.s; a.ehyd = (R)d.oyh.d;
         a.c1xs = a.ehxs; a.c1xd = a.ehxd; a.c1ys = a.ehys; a.c1yd = a.ehyd;
     } else {
-        tangent_stage<R>(ox1, oy1, d, true, a.o1xs, a.o1xd, a.o1ys);
-        tangent_stage<R>(d.ox2, d.oy2, d, true, a.o2xs, a.o2xd, a.o2ys);
-        tangent_stage<R>(d.oxh, d.oyh, d, false, a.c1xs, a.c1xd, a.c1ys);
-        a.ehxs = (R)std::tan(d.oxh.al);
-        a.ehys = (R)std::tan(d.oyh.al);
+        const R tex = tangent<R>(d.oxh), tey = tangent<R>(d.oyh);
+        const double Le = 2.0 * log_sec2(tex) + 2.0 * log_sec2(tey);  // four even factors
+        a.ehxs = tex;
+        a.ehys = tey;
+        a.o1ys = tangent<R>(oy1);
+        a.o2ys = tangent<R>(d.oy2);
+        a.c1ys = tangent<R>(d.oyh);
         a.o1yd = a.o2yd = a.c1yd = a.ehxd = a.ehyd = R(0);
+        // closing stage: odd x and y at dt/2, no table
+        delta_odd_x<R>(d.oxh.al, log_sec2(a.c1ys), a.c1xs, a.c1xd);
+        if (d.td) {
+            // every stage's odd x factor restores that stage's cosines
+            delta_odd_x<R>(ox1.al, Le + log_sec2(a.o1ys), a.o1xs, a.o1xd);
+            delta_odd_x<R>(d.ox2.al, Le + log_sec2(a.o2ys), a.o2xs, a.o2xd);
+        } else {
+            // the table restores a steady step's cosines (L_step); stage 0 of the
+            // first pass restores the rest of its own
+            a.o2xs = tangent<R>(d.ox2);
+            a.o2xd = R(0);
+            if (d.first) {
+                const double L_step = step_log_sec2<R>(d.oxh, d.oyh, d.ox2, d.oy2);
+                delta_odd_x<R>(ox1.al, Le + log_sec2(a.o1ys) - L_step, a.o1xs, a.o1xd);
+            } else {
+                a.o1xs = a.o2xs;
+                a.o1xd = R(0);
+            }
+        }
     }
     for (int k = 0; k < kMaxSteps; ++k) a.g[k] = (d.td && d.f && k < d.steps) ? d.f[k] : 0.0;
     return a;
@@ -154,8 +193,9 @@ bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, b
                           bool closed = false, bool td = false);
 
 // All launchers return hipSuccess or the launch error.
+// exp(-i dt (V + eps0) / hbar) times `scale` per site.
 hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long sites,
-                              double dt, double eps0, double hbar, hipStream_t s);
+                              double dt, double eps0, double hbar, double scale, hipStream_t s);
 // Table of the time-dependent potential V0 + f(t) W: per site the phase angle
 // theta0 = dt (V0 + eps0) / hbar and its modulation w = dt W / hbar, as a
 // double2 (16 B/site, both dtypes); step n's phase is exp(-i (theta0 + f_n w)).

@@ -56,27 +56,29 @@ Variant variant_of(bool batch, bool closed, bool td) {
 
 // ------------------------------------------------------------------ phase table of H0 (Sec. 2)
 
+// `g` scales every entry (the product of a step's cosines on periodic meshes,
+// else 1).
 __global__ void phase_table_c128(const double* __restrict__ V, double2* __restrict__ P,
-                                 long long n, double dt, double eps0, double hbar) {
+                                 long long n, double dt, double eps0, double hbar, double g) {
     for (long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x; l < n;
          l += (long long)gridDim.x * blockDim.x) {
         double phi = dt * (V[l] + eps0) / hbar;
         double s, c;
         sincos(phi, &s, &c);
-        P[l] = make_double2(c, -s);
+        P[l] = make_double2(g * c, -(g * s));
     }
 }
 
 // complex64: cos(phi) and -sin(phi) as 32-bit fixed point, value * 2^30
 // rounded to nearest (|value| <= 1, so 2^30 fits; error <= 2^-31 per part).
 __global__ void phase_table_c64(const double* __restrict__ V, int2* __restrict__ P,
-                                long long n, double dt, double eps0, double hbar) {
+                                long long n, double dt, double eps0, double hbar, double g) {
     for (long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x; l < n;
          l += (long long)gridDim.x * blockDim.x) {
         double phi = dt * (V[l] + eps0) / hbar;
         double s, c;
         sincos(phi, &s, &c);
-        P[l] = make_int2(__double2int_rn(c * 0x1p30), __double2int_rn(-s * 0x1p30));
+        P[l] = make_int2(__double2int_rn(g * c * 0x1p30), __double2int_rn(-(g * s) * 0x1p30));
     }
 }
 
@@ -103,33 +105,51 @@ __device__ __forceinline__ void load_site(const void* psi, long long l, double& 
     im = (double)v.y;
 }
 
+// Block b sums |psi|^2 and Re(conj(psi) (H psi)) over its share of the mesh:
+// work items (column chunk of kReduceThreads columns, band of `band` rows),
+// items b, b + gridDim.x, ...; each thread walks its column down the band with
+// the rows above and below the current one in registers, so every psi and V
+// value is read once from device memory (the x-neighbours come from the cache
+// lines the wavefront has just read).  Fixed item order and a fixed in-block
+// tree: the result is bitwise reproducible.
 template <class T>
 __global__ void __launch_bounds__(kReduceThreads)
 observables_partial(const void* __restrict__ psi, const double* __restrict__ V, int nx, int ny,
-                    double Jx, double Jy, double eps0, int closed, double* __restrict__ partial) {
+                    double Jx, double Jy, double eps0, int closed, int band,
+                    double* __restrict__ partial) {
     __shared__ double sn[kReduceThreads], se[kReduceThreads];
     double an = 0.0, ae = 0.0;
-    for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+    const int chunks = (nx + kReduceThreads - 1) / kReduceThreads;
+    const int bands = (ny + band - 1) / band;
+    const long long items = (long long)chunks * bands;
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+        const int x = (int)(it % chunks) * kReduceThreads + (int)threadIdx.x;
+        const int y0 = (int)(it / chunks) * band;
+        const int y1 = min(y0 + band, ny);
+        if (x >= nx) continue;
         // neighbours wrap on periodic meshes and are absent beyond closed walls
-        const bool has_yp = !closed || y + 1 < ny, has_ym = !closed || y > 0;
-        const int yp = (y + 1 == ny) ? 0 : y + 1;
-        const int ym = (y == 0) ? ny - 1 : y - 1;
-        const long long row = (long long)y * nx;
-        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const bool has_xp = !closed || x + 1 < nx, has_xm = !closed || x > 0;
-            const int xp = (x + 1 == nx) ? 0 : x + 1;
-            const int xm = (x == 0) ? nx - 1 : x - 1;
-            double r, i, r1 = 0, i1 = 0, r2 = 0, i2 = 0, r3 = 0, i3 = 0, r4 = 0, i4 = 0;
-            load_site(psi, row + x, r, i, T());
+        const bool has_xp = !closed || x + 1 < nx, has_xm = !closed || x > 0;
+        const int xp = (x + 1 == nx) ? 0 : x + 1;
+        const int xm = (x == 0) ? nx - 1 : x - 1;
+        double ur = 0, ui = 0, cr, ci;  // row above, current row
+        if (!closed || y0 > 0)
+            load_site(psi, (long long)(y0 == 0 ? ny - 1 : y0 - 1) * nx + x, ur, ui, T());
+        load_site(psi, (long long)y0 * nx + x, cr, ci, T());
+        for (int y = y0; y < y1; ++y) {
+            double dr = 0, di = 0;  // row below
+            if (!closed || y + 1 < ny)
+                load_site(psi, (long long)(y + 1 == ny ? 0 : y + 1) * nx + x, dr, di, T());
+            const long long row = (long long)y * nx;
+            double r1 = 0, i1 = 0, r2 = 0, i2 = 0;
             if (has_xp) load_site(psi, row + xp, r1, i1, T());
             if (has_xm) load_site(psi, row + xm, r2, i2, T());
-            if (has_yp) load_site(psi, (long long)yp * nx + x, r3, i3, T());
-            if (has_ym) load_site(psi, (long long)ym * nx + x, r4, i4, T());
             const double diag = V[row + x] + eps0;
-            const double hr = diag * r - Jx * (r1 + r2) - Jy * (r3 + r4);
-            const double hi = diag * i - Jx * (i1 + i2) - Jy * (i3 + i4);
-            an += r * r + i * i;
-            ae += r * hr + i * hi;
+            const double hr = diag * cr - Jx * (r1 + r2) - Jy * (dr + ur);
+            const double hi = diag * ci - Jx * (i1 + i2) - Jy * (di + ui);
+            an += cr * cr + ci * ci;
+            ae += cr * hr + ci * hi;
+            ur = cr; ui = ci;
+            cr = dr; ci = di;
         }
     }
     sn[threadIdx.x] = an;
@@ -200,16 +220,16 @@ MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per
 }
 
 hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long sites,
-                              double dt, double eps0, double hbar, hipStream_t s) {
+                              double dt, double eps0, double hbar, double scale, hipStream_t s) {
     const int threads = 256;
     long long want = (sites + threads - 1) / threads;
     const int blocks = (int)(want < 8192 ? want : 8192);
     if (dtype == 1)
         hipLaunchKernelGGL(phase_table_c128, dim3(blocks), dim3(threads), 0, s, V,
-                           reinterpret_cast<double2*>(ptab), sites, dt, eps0, hbar);
+                           reinterpret_cast<double2*>(ptab), sites, dt, eps0, hbar, scale);
     else
         hipLaunchKernelGGL(phase_table_c64, dim3(blocks), dim3(threads), 0, s, V,
-                           reinterpret_cast<int2*>(ptab), sites, dt, eps0, hbar);
+                           reinterpret_cast<int2*>(ptab), sites, dt, eps0, hbar, scale);
     return hipGetLastError();
 }
 
@@ -273,12 +293,20 @@ hipError_t launch_observables(int dtype, const void* psi, const double* V, int n
                               double Jx, double Jy, double eps0, bool closed, double* partial,
                               int nblocks, double* result, hipStream_t s) {
     const int cl = closed ? 1 : 0;
+    // bands of rows sized so the work items fill `nblocks` blocks once
+    const long long chunks = (nx + kReduceThreads - 1) / kReduceThreads;
+    long long bands = nblocks / chunks;
+    if (bands < 1) bands = 1;
+    if (bands > ny) bands = ny;
+    const int band = (int)((ny + bands - 1) / bands);
+    const long long items = chunks * ((ny + band - 1) / band);
+    if (items < nblocks) nblocks = (int)items;
     if (dtype == 1)
         hipLaunchKernelGGL(observables_partial<C128>, dim3(nblocks), dim3(kReduceThreads), 0, s,
-                           psi, V, nx, ny, Jx, Jy, eps0, cl, partial);
+                           psi, V, nx, ny, Jx, Jy, eps0, cl, band, partial);
     else
         hipLaunchKernelGGL(observables_partial<C64>, dim3(nblocks), dim3(kReduceThreads), 0, s,
-                           psi, V, nx, ny, Jx, Jy, eps0, cl, partial);
+                           psi, V, nx, ny, Jx, Jy, eps0, cl, band, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(observables_final, dim3(1), dim3(kReduceThreads), 0, s, partial, nblocks,

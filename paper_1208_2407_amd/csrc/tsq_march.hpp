@@ -293,6 +293,21 @@ __device__ __forceinline__ void even_x(Row<R, SPL>& w, R s, R d, const XPairs<SP
     }
 }
 
+// Odd x-pairs in the tangent form (periodic meshes): inner ones inside the
+// lane, the two at the lane edges across lanes.
+template <class R, int SPL>
+__device__ __forceinline__ void odd_x_t(Row<R, SPL>& w, R t) {
+    const R rr = from_right(w.re[0]), ri = from_right(w.im[0]);
+    const R lr = from_left(w.re[SPL - 1]), li = from_left(w.im[SPL - 1]);
+#pragma unroll
+    for (int p = 0; p + 1 < SPL / 2; ++p)
+        rot_pair_t(w.re[2 * p + 1], w.im[2 * p + 1], w.re[2 * p + 2], w.im[2 * p + 2], t);
+    w.re[SPL - 1] = mad(-t, ri, w.re[SPL - 1]);
+    w.im[SPL - 1] = mad(t, rr, w.im[SPL - 1]);
+    w.re[0] = mad(-t, li, w.re[0]);
+    w.im[0] = mad(t, lr, w.im[0]);
+}
+
 // Odd x-pairs: inner ones inside the lane, the two at the lane edges across lanes.
 template <bool CLOSED, class R, int SPL>
 __device__ __forceinline__ void odd_x(Row<R, SPL>& w, R s, R d, const XPairs<SPL / 2, CLOSED>& m) {
@@ -401,8 +416,9 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // step k's factor from a.g[k].  Closed meshes rotate the y-pairs that cross
 // a wall with zero coefficients (`qk` is the pair stage k completes; a
 // wavefront-uniform test) and apply every factor in the delta form; periodic
-// meshes apply the even and odd y factors in the tangent form and the odd x
-// factor, which every site meets once per stage, with the stage's cosines.
+// meshes apply the tangent form, the odd x factors of stage 0 and of the
+// closing stage (and of every stage under a time-dependent potential) in the
+// delta form that restores the cosines (see MarchArgs).
 template <int S, int K, bool CLOSED, bool TD, class R, int SPL, class PT, class PhaseFn>
 __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
                                                const MarchArgs<R>& a,
@@ -418,8 +434,13 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
     }
     if constexpr (!CLOSED) {
         (void)oyd; (void)qk; (void)rev;
-        odd_x<false>(o.g, oxs, oxd, xm);
-        odd_x<false>(n.f, oxs, oxd, xm);
+        if (TD || k == 0 || k == S) {
+            odd_x<false>(o.g, oxs, oxd, xm);
+            odd_x<false>(n.f, oxs, oxd, xm);
+        } else {
+            odd_x_t(o.g, oxs);
+            odd_x_t(n.f, oxs);
+        }
         pair_y_t(o.g, n.f, oys);
         if (k < S) {
             const PhasePair<PT, SPL> ph = phase(k);
