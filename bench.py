@@ -104,11 +104,12 @@ def committed_traffic(dtype: str, schedule, nx: int, ny: int, nz: int = 0) -> fl
     return float(e["bytes_per_launch"])
 
 
-def alg_bytes_per_site(dtype: str) -> int:
+def alg_bytes_per_site(dtype: str, tables: int = 1) -> int:
     """Algorithmic HBM bytes per site of one fused pass: read psi, write psi and
-    read the phase factor, each in the working dtype (16 B complex128, 8 B
+    read the phase factor of each sub-step kind in the pass (one; two for a
+    fourth-order pass), each in the working dtype (16 B complex128, 8 B
     complex64)."""
-    return 3 * (16 if dtype == "c128" else 8)
+    return (2 + tables) * (16 if dtype == "c128" else 8)
 
 
 # Bytes per site the library's phase table holds: complex128 exp(-i phi) (16);
@@ -117,19 +118,20 @@ TABLE_BYTES_PER_SITE = {"c128": 16, "c64": 8}
 
 
 def roofline(dtype: str, sites: int, launch_s: float, site_steps_per_s: float, traffic,
-             kernel: str = "march_kernel") -> dict:
-    """Roofline object of one pass: algorithmic bytes per launch (SURVEY-style 3 x
-    elem per site) over the measured average launch time, against 8 TB/s."""
-    alg = sites * alg_bytes_per_site(dtype)
+             kernel: str = "march_kernel", tables: int = 1) -> dict:
+    """Roofline object of one pass: algorithmic bytes per launch (read and write
+    psi, read each phase table, per site, in the working dtype) over the measured
+    average launch time, against 8 TB/s."""
+    alg = sites * alg_bytes_per_site(dtype, tables)
     achieved = alg / launch_s / 1e9
     elem = 16 if dtype == "c128" else 8
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
            "kernel": kernel, "avg_launch_us": round(launch_s * 1e6, 2),
            "algorithmic_bytes_per_launch": alg,
-           "algorithmic_bytes_per_site": alg_bytes_per_site(dtype),
+           "algorithmic_bytes_per_site": alg_bytes_per_site(dtype, tables),
            # table bytes the pass reads beyond the working dtype's size (0 for both)
-           "table_extra_bytes_per_launch": sites * (TABLE_BYTES_PER_SITE[dtype] - elem),
+           "table_extra_bytes_per_launch": tables * sites * (TABLE_BYTES_PER_SITE[dtype] - elem),
            # one pass per step would move the algorithmic bytes every step: how
            # far fusion takes the solve past that kernel's roofline (> 1)
            "eff_frac_one_pass_per_step": round(site_steps_per_s * alg_bytes_per_site(dtype)
@@ -208,7 +210,9 @@ def run_dtype(dtype: str, p, psi0, V, args, order: int = 2, bc: str = "periodic"
                      "pairs_per_lane": sched[2],
                      "phase_store": {1: "registers", 2: "lds"}[sched[3]],
                      "passes_per_solve": passes, "copy_back": copy_back},
-        "roofline": roofline(dtype, p.nx * p.ny, launch_s, site_steps / wall, traffic),
+        # a fourth-order pass on a periodic mesh reads both sub-step tables
+        "roofline": roofline(dtype, p.nx * p.ny, launch_s, site_steps / wall, traffic,
+                             tables=2 if order == 4 and bc == "periodic" else 1),
         "precision": {"norm_start": n0, "norm_end": n1, "norm_drift": n1 - n0,
                       "energy_start": e0, "energy_end": e1, "energy_drift": e1 - e0},
     }

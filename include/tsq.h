@@ -154,7 +154,9 @@ int tsq_plan_get_schedule(const tsq_plan* plan, tsq_schedule* schedule);
 /* Number of kernel launches (fused passes) tsq_evolve (or, after
  * tsq_set_potential_td, tsq_evolve_td) makes for `steps`
  * under the plan's schedule, and whether it ends with a device-to-device copy
- * (odd pass count that cannot be split).  Host only.  Errors: TSQ_ERR_ARG. */
+ * (odd pass count that cannot be split).  Order-4 plans of periodic 2D meshes
+ * run one pass per fourth-order step (its five second-order sub-steps fused,
+ * whatever steps_per_pass says).  Host only.  Errors: TSQ_ERR_ARG. */
 int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int32_t* copy_back);
 
 /* The diagonal part H0 of Sec. 2 (potential plus the mesh's on-site term

@@ -1,0 +1,10 @@
+// March kernel instances: complex64, fourth order in one pass per step.
+#include "tsq_march.hpp"
+
+namespace tsq {
+
+const void* march_ptr_c64_order4(int steps, bool last, int ppl, bool lds) {
+    return pick_kernel<C64, Variant::Order4>(steps, last, ppl, lds);
+}
+
+}  // namespace tsq

@@ -121,14 +121,15 @@ int device_cus() {
     return g_dev.cus;
 }
 
-int occupancy_cached(int dtype, int steps, bool last, int ppl, bool lds, bool closed, bool td) {
-    // [dtype][steps][last][ppl][lds][closed][td]; 0 = not yet queried
-    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3][2][2][2];
-    std::atomic<int>& slot =
-        table[dtype & 1][steps][last ? 1 : 0][ppl][lds ? 1 : 0][closed ? 1 : 0][td ? 1 : 0];
+int occupancy_cached(int dtype, int steps, bool last, int ppl, bool lds, bool closed, bool td,
+                     bool u4 = false) {
+    // [dtype][steps][last][ppl][lds][closed][td][u4]; 0 = not yet queried
+    static std::atomic<int> table[2][tsq::kMaxSteps + 1][2][3][2][2][2][2];
+    std::atomic<int>& slot = table[dtype & 1][steps][last ? 1 : 0][ppl][lds ? 1 : 0][closed ? 1 : 0]
+                                  [td ? 1 : 0][u4 ? 1 : 0];
     int v = slot.load(std::memory_order_relaxed);
     if (v == 0) {
-        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl, lds, false, closed, td);
+        v = tsq::march_blocks_per_cu(dtype, steps, last, ppl, lds, false, closed, td, u4);
         if (v <= 0) v = 1;
         slot.store(v, std::memory_order_relaxed);
     }
@@ -136,12 +137,12 @@ int occupancy_cached(int dtype, int steps, bool last, int ppl, bool lds, bool cl
 }
 
 int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl, bool lds, bool closed,
-                     bool td) {
+                     bool td, bool u4 = false) {
     const tsq::MarchGeometry g = tsq::march_geometry(p->p.nx, p->p.ny, steps, last, ppl, 2);
     int cus = device_cus();
     if (cus <= 0) cus = 256;
     const long long slots =
-        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl, lds, closed, td) *
+        (long long)cus * occupancy_cached(p->p.dtype, steps, last, ppl, lds, closed, td, u4) *
         tsq::kWavesPerBlock;
     const long long pairs = (p->p.ny + 1) / 2;
     // a launch has one block per segment of kWavesPerBlock strips
@@ -154,6 +155,22 @@ int default_seg_rows(const tsq_plan* p, int steps, bool last, int ppl, bool lds,
     const long long min_pairs = 2LL * (steps + (last ? 1 : 0));
     if (pairs_per_seg < min_pairs) pairs_per_seg = min_pairs;
     return (int)(2 * pairs_per_seg);
+}
+
+// Fourth order on a periodic 2D mesh runs one pass per fourth-order step (its
+// five sub-steps fused, both phase tables read in the pass).
+bool fused_order4(const tsq_plan* p) {
+    return p->p.order == 4 && !p->three_d && p->p.bc == TSQ_BC_PERIODIC;
+}
+
+// -2 log of the scale the phase table of sub-step kind k carries: on periodic
+// 2D meshes the cosines of a steady step of that kind (the tangent-form factors
+// leave them out), from the tangents rounded in the plan's dtype; else 0.
+double table_log(const tsq_plan* p, int k) {
+    if (p->three_d || p->p.bc != TSQ_BC_PERIODIC) return 0.0;
+    const SubStep& u = p->kind[k];
+    return p->p.dtype == TSQ_C128 ? tsq::step_log_sec2<double>(u.oxh, u.oyh, u.ox2, u.oy2)
+                                  : tsq::step_log_sec2<float>(u.oxh, u.oyh, u.ox2, u.oy2);
 }
 
 // Pass sizes as runs of (steps per pass, repeat): S steps each, the remainder
@@ -750,6 +767,11 @@ int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int3
         *copy_back = (steps > 0 && !(steps & 1)) ? 1 : 0;
         return ok();
     }
+    if (fused_order4(plan)) {  // one pass per fourth-order step
+        *passes = steps;
+        *copy_back = (steps & 1) ? 1 : 0;
+        return ok();
+    }
     std::vector<PassGroup> groups;
     const int S = plan->td ? std::min(plan->sched.steps_per_pass, tsq::kMaxTdSteps)
                            : plan->sched.steps_per_pass;
@@ -769,13 +791,8 @@ int tsq_set_potential(tsq_plan* plan, const double* V, void* ws, size_t ws_bytes
     for (int k = 0; k < plan->nkinds; ++k) {
         const SubStep& u = plan->kind[k];
         // periodic 2D meshes: the table carries a step's cosines (the march's
-        // tangent-form factors leave them out), from the tangents as rounded
-        // in the plan's dtype
-        double scale = 1.0;
-        if (!plan->three_d && plan->p.bc == TSQ_BC_PERIODIC)
-            scale = std::exp(-0.5 * (plan->p.dtype == TSQ_C128
-                                         ? tsq::step_log_sec2<double>(u.oxh, u.oyh, u.ox2, u.oy2)
-                                         : tsq::step_log_sec2<float>(u.oxh, u.oyh, u.ox2, u.oy2)));
+        // tangent-form factors leave them out)
+        const double scale = std::exp(-0.5 * table_log(plan, k));
         hipError_t e = tsq::launch_phase_table(plan->p.dtype, V, w + u.off_ptab,
                                                (long long)plan->sites, u.dt, plan->eps0,
                                                plan->p.hbar, scale,
@@ -828,10 +845,53 @@ int check_evolve(const tsq_plan* plan, const void* psi, int64_t steps, const voi
     return TSQ_OK;
 }
 
+// Fourth order on a periodic 2D mesh: one pass per step, sub-steps p, p, m,
+// p, p with both phase tables; an odd pass count ends with a copy back.
+int run_evolution_order4(tsq_plan* plan, void* psi, int64_t steps, void* ws, hipStream_t s) {
+    char* w = static_cast<char*>(ws);
+    void* buf[2] = {psi, w + plan->off_psi2};
+    tsq::PassDesc d;
+    d.nx = plan->p.nx;
+    d.ny = plan->p.ny;
+    d.pairs_per_lane = 1;
+    d.phase_lds = true;
+    d.u4 = true;
+    d.steps = 5;
+    const SubStep& p = plan->kind[0];
+    const SubStep& m = plan->kind[1];
+    d.ptab = w + p.off_ptab;
+    d.ptab2 = w + m.off_ptab;
+    d.oxh = p.oxh;
+    d.oyh = p.oyh;
+    d.ox2 = p.ox2;
+    d.oy2 = p.oy2;
+    d.mxh = m.oxh;
+    d.myh = m.oyh;
+    d.log_table_p = table_log(plan, 0);
+    d.log_table_m = table_log(plan, 1);
+    for (int64_t i = 0; i < steps; ++i) {
+        d.src = buf[i & 1];
+        d.dst = buf[(i + 1) & 1];
+        d.first = i == 0;
+        d.last = i + 1 == steps;
+        d.seg_rows = plan->sched.segment_rows
+                         ? plan->sched.segment_rows
+                         : default_seg_rows(plan, 5, d.last, 1, true, false, false, true);
+        hipError_t e = tsq::launch_pass(plan->p.dtype, d, s);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "order-4 pass launch: %s", hipGetErrorString(e));
+    }
+    if (steps & 1) {
+        hipError_t e = hipMemcpyAsync(psi, buf[1], plan->sites * plan->elem, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "copy back: %s", hipGetErrorString(e));
+    }
+    return ok();
+}
+
 // Launch the passes of `steps` steps (f: per-step modulation of a
 // time-dependent potential, else null) and the copy back if any.
 int run_evolution(tsq_plan* plan, void* psi, int64_t steps, void* ws, hipStream_t s,
                   const double* f) {
+    if (!f && fused_order4(plan)) return run_evolution_order4(plan, psi, steps, ws, s);
     char* w = static_cast<char*>(ws);
     void* buf[2] = {psi, w + plan->off_psi2};
     const bool td = f != nullptr;

@@ -36,6 +36,12 @@ struct PassDesc {
     const double* f = nullptr;  // td: modulation f_n of this pass's steps (host, `steps` values)
     Coef64 oxh, oyh;      // tau = dt/2 along x, y
     Coef64 ox2, oy2;      // tau = dt along x, y
+    // fourth order in one pass per step (periodic): sub-steps p, p, m, p, p;
+    // the fields above are those of the p sub-step, these of the m sub-step
+    bool u4 = false;
+    const void* ptab2 = nullptr;  // phase table of the m sub-step
+    Coef64 mxh, myh;              // m sub-step, tau = its dt / 2
+    double log_table_p = 0.0, log_table_m = 0.0;  // -2 log of each table's scale
 };
 
 constexpr int kMaxSteps = 8;     // deepest fusion (phase ring in LDS)
@@ -82,17 +88,28 @@ MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per
 //   o2xs tangent / (s', d') (td)         o2ys  odd y tangent
 //   c1x* (s', d')  closing odd x         c1ys  closing odd y tangent
 //   ehxs, ehys     even tangents
+// Per-stage coefficients of the fourth-order pass (stages 0..4, closing 5):
+// odd x (s', d') and odd y tangent per stage; even tangents per sub-step kind
+// (0 = p, 1 = m).
+template <class R>
+struct Order4Coefs {
+    R xs[6], xd[6], yt[6];
+    R ext[2], eyt[2];
+};
+
 template <class R>
 struct MarchArgs {
     const void* src;
     void* dst;
     const void* ptab;
+    const void* ptab2;  // fourth order: the m sub-step's table
     int nx, ny, strip_sites, seg_rows, nstrips, nsegs;
     R o1xs, o1xd, o1ys, o1yd;  // odd factors opening the pass: tau = dt/2 (first pass) or dt
     R o2xs, o2xd, o2ys, o2yd;  // odd factors between steps, tau = dt
     R ehxs, ehxd, ehys, ehyd;  // even factors, tau = dt/2
     R c1xs, c1xd, c1ys, c1yd;  // odd factors closing the evolution, tau = dt/2
     double g[kMaxSteps];       // time-dependent potential: f_n of step k of the pass
+    Order4Coefs<R> u4;         // fourth order in one pass per step
 };
 
 // Tangent-form coefficients (periodic meshes), rounded to R.
@@ -174,6 +191,32 @@ MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
         }
     }
     for (int k = 0; k < kMaxSteps; ++k) a.g[k] = (d.td && d.f && k < d.steps) ? d.f[k] : 0.0;
+    a.ptab2 = d.ptab2;
+    a.u4 = Order4Coefs<R>{};
+    if (d.u4) {
+        // sub-step kinds p, p, m, p, p; the odd factor ahead of sub-step k
+        // merges the half factors of sub-steps k-1 and k (Eq. "fourthorder"
+        // as consecutive second-order steps), or opens the evolution
+        const Coef64* hx[2] = {&d.oxh, &d.mxh};
+        const Coef64* hy[2] = {&d.oyh, &d.myh};
+        const int kind[5] = {0, 0, 1, 0, 0};
+        const double Ltab[2] = {d.log_table_p, d.log_table_m};
+        for (int q = 0; q < 2; ++q) {
+            a.u4.ext[q] = tangent<R>(*hx[q]);
+            a.u4.eyt[q] = tangent<R>(*hy[q]);
+        }
+        for (int k = 0; k <= 5; ++k) {
+            const int cur = k < 5 ? kind[k] : 0, prev = k > 0 ? kind[k - 1] : 0;
+            const bool open = k == 0 && d.first, close = k == 5;
+            const double alx = (open ? 0.0 : hx[prev]->al) + (close ? 0.0 : hx[cur]->al);
+            const double aly = (open ? 0.0 : hy[prev]->al) + (close ? 0.0 : hy[cur]->al);
+            a.u4.yt[k] = (R)std::tan(aly);
+            double L = log_sec2(a.u4.yt[k]);
+            if (!close)
+                L += 2.0 * log_sec2(a.u4.ext[cur]) + 2.0 * log_sec2(a.u4.eyt[cur]) - Ltab[cur];
+            delta_odd_x<R>(alx, L, a.u4.xs[k], a.u4.xd[k]);
+        }
+    }
     return a;
 }
 
@@ -188,7 +231,7 @@ struct BatchTile {
 // Resident blocks per compute unit of one march kernel instance (0 if the
 // query fails); used to size segments so a pass is one round of resident waves.
 int march_blocks_per_cu(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
-                        bool batch = false, bool closed = false, bool td = false);
+                        bool batch = false, bool closed = false, bool td = false, bool u4 = false);
 bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, bool phase_lds,
                           bool closed = false, bool td = false);
 
@@ -215,7 +258,7 @@ hipError_t launch_observables(int dtype, const void* psi, const double* V, int n
                               double Jx, double Jy, double eps0, bool closed, double* partial,
                               int nblocks, double* result, hipStream_t s);
 
-constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBlocks = 8192;  // partial sums of the norm and energy reductions
 
 // Bytes of the library-held device array of tsq_batch_evolve_noalloc (per GPU).
 constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;

@@ -400,6 +400,8 @@ struct PhasePair {
     PT f[SPL], g[SPL];
 };
 
+__device__ __forceinline__ int rstep_of(bool rev) { return rev ? -2 : 2; }
+
 __device__ __forceinline__ int wrap(long long v, int n) {
     long long m = v % n;
     return (int)(m < 0 ? m + n : m);
@@ -419,11 +421,34 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // meshes apply the tangent form, the odd x factors of stage 0 and of the
 // closing stage (and of every stage under a time-dependent potential) in the
 // delta form that restores the cosines (see MarchArgs).
-template <int S, int K, bool CLOSED, bool TD, class R, int SPL, class PT, class PhaseFn>
+template <int S, int K, bool CLOSED, bool TD, bool U4, class R, int SPL, class PT, class PhaseFn>
 __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
                                                const MarchArgs<R>& a,
                                                const XPairs<SPL / 2, CLOSED>& xm, int qk, bool rev,
                                                PhaseFn&& phase) {
+    if constexpr (U4) {
+        // one fourth-order step: sub-steps p, p, m, p, p (Eq. "fourthorder");
+        // stage k's odd x factor (delta form) carries its own cosines over
+        // those its table holds, its odd y and even factors are tangents of
+        // its kinds, stage 2 takes the m table
+        (void)qk; (void)rev;
+        odd_x<false>(o.g, a.u4.xs[k], a.u4.xd[k], xm);
+        odd_x<false>(n.f, a.u4.xs[k], a.u4.xd[k], xm);
+        pair_y_t(o.g, n.f, a.u4.yt[k]);
+        if (k < S) {
+            const int q = k == 2 ? 1 : 0;
+            const PhasePair<PT, SPL> ph = phase(k);
+            even_x_t(o.f, a.u4.ext[q]);
+            even_x_t(o.g, a.u4.ext[q]);
+            pair_y_t(o.f, o.g, a.u4.eyt[q]);
+            phase_row(o.f, ph.f);
+            phase_row(o.g, ph.g);
+            pair_y_t(o.f, o.g, a.u4.eyt[q]);
+            even_x_t(o.f, a.u4.ext[q]);
+            even_x_t(o.g, a.u4.ext[q]);
+        }
+        return;
+    }
     R oxs, oxd, oys, oyd;
     if (k == 0) {
         oxs = a.o1xs; oxd = a.o1xd; oys = a.o1ys; oyd = a.o1yd;
@@ -548,7 +573,7 @@ using PhaseT = std::conditional_t<TD, double2, typename T::PT>;
 template <class T, bool TD>
 using TableT = std::conditional_t<TD, double2, typename T::TT>;
 
-template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD>
+template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD, bool U4>
 __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, int strip, int seg,
                                            bool rev, int lane, PhaseT<T, TD>* ring) {
     using R = typename T::R;
@@ -559,6 +584,8 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     constexpr int NL = WaveRing<PT, S, PPL, LDS>::kSlots;
     constexpr int NH = LDS ? ((K + 3) & ~1) : K + 2;  // even with the LDS ring
     constexpr int NP = LDS ? 2 : NH;                   // phase homes
+    static_assert(!U4 || (LDS && S == 5 && !CLOSED && !TD && PPL == 1),
+                  "the fourth-order pass is 5 sub-steps, LDS ring, periodic, one pair per lane");
     const int nx = a.nx, ny = a.ny;
 
     // x: unwrapped column of the lane's first site; wrapped (periodic) or
@@ -613,6 +640,16 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     const int fo = rev ? 1 : 0;  // row offset of F within a pair; G is at 1 - fo
     int rpsi = CLOSED ? 2 * tstart : wrap(2LL * tstart, ny);
     int rph = rpsi;
+    // fourth order: the m-table phase of the pair stage 2 completes in the
+    // next iteration, i.e. two pairs behind the pair whose phase `rph` loads
+    int rphm = rpsi;
+    if constexpr (U4) {
+        rphm -= 2 * rstep_of(rev);
+        if constexpr (!CLOSED) {
+            rphm = rphm < 0 ? rphm + ny : rphm;
+            rphm = rphm >= ny ? rphm - ny : rphm;
+        }
+    }
     int qout = rev ? q1 - 1 + 2 * K : q0 - 2 * K;  // pair leaving the pipeline this iteration
 
     const int rstep = rev ? -2 : 2;
@@ -659,6 +696,23 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         load_phase_row(rph + 1 - fo, ph.g);
         step_row(rph);
     };
+    auto load_phase_m = [&](PhasePair<PT, SPL>& ph) {
+        if constexpr (U4) {
+            const typename T::TT* P = reinterpret_cast<const typename T::TT*>(a.ptab2);
+            const long long offf = (long long)(rphm + fo) * nx;
+            const long long offg = (long long)(rphm + 1 - fo) * nx;
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                ph.f[2 * p] = decode_phase(P[offf + col[p]]);
+                ph.f[2 * p + 1] = decode_phase(P[offf + col[p] + 1]);
+                ph.g[2 * p] = decode_phase(P[offg + col[p]]);
+                ph.g[2 * p + 1] = decode_phase(P[offg + col[p] + 1]);
+            }
+            step_row(rphm);
+        } else {
+            (void)ph;
+        }
+    };
     auto store_out = [&](const PairRows<R, SPL>& h) {
         const int qo = qout;
         qout += rev ? -1 : 1;
@@ -685,6 +739,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
 
     PairRows<R, SPL> home[NH];
     PhasePair<PT, SPL> ph[NP];
+    PhasePair<PT, SPL> phm[U4 ? 2 : 1];  // m-table phases (fourth order), two homes
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
 #pragma unroll
@@ -697,6 +752,11 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     for (int h = 0; h < NP; ++h) {
 #pragma unroll
         for (int i = 0; i < SPL; ++i) ph[h].f[i] = ph[h].g[i] = zero_phase<PT>();
+    }
+#pragma unroll
+    for (int h = 0; h < (U4 ? 2 : 1); ++h) {
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) phm[h].f[i] = phm[h].g[i] = zero_phase<PT>();
     }
 
     constexpr int SLOT = 2 * SPL * kWaveSize;  // PT elements per LDS slot
@@ -718,12 +778,14 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         // merges.
         load_psi(home[(u + 1) % NH]);
         load_phase(ph[u % NP]);
+        if constexpr (U4) load_phase_m(phm[(u + 1) % 2]);
         static_for<K>([&](auto KK) {
             constexpr int k = decltype(KK)::value;
             if (it > 2 * k)
-            pipeline_stage<S, K, CLOSED, TD, R, SPL, PT>(
+            pipeline_stage<S, K, CLOSED, TD, U4, R, SPL, PT>(
                 k, home[(u - 1 - k + 2 * NH) % NH], home[(u - k + 2 * NH) % NH], a, xm,
                 rev ? q + k : q - k, rev, [&](int kk) {
+                    if (U4 && kk == 2) return phm[U4 ? u % 2 : 0];
                     if (!LDS || kk == 0) return ph[(u - 1 - kk + 2 * NP) % NP];
                     int slot = wslot - kk;
                     if (slot < 0) slot += NL;
@@ -761,7 +823,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
 }
 
 // One problem, one tile per wavefront.
-template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD>
+template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD, bool U4 = false>
 __global__ void __launch_bounds__(kWaveSize * kWavesPerBlock)
 march_kernel(const MarchArgs<typename T::R> a) {
     __shared__ WaveRing<PhaseT<T, TD>, S, PPL, LDS> rings[LDS ? kWavesPerBlock : 1];
@@ -784,7 +846,7 @@ march_kernel(const MarchArgs<typename T::R> a) {
     const int seg = lb - grp * a.nsegs;
     const int strip = grp * kWavesPerBlock + wave;
     if (strip >= a.nstrips) return;  // uniform per wavefront
-    march_tile<T, S, LAST, PPL, LDS, CLOSED, TD>(a, strip, seg, seg & 1, lane,
+    march_tile<T, S, LAST, PPL, LDS, CLOSED, TD, U4>(a, strip, seg, seg & 1, lane,
                                                  &rings[LDS ? wave : 0].v[0][0][0][lane]);
 }
 
@@ -802,7 +864,7 @@ march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
     for (int i = blockIdx.x * kWavesPerBlock + wave; i < ntiles; i += nw) {
         const BatchTile t = tiles[i];
         const MarchArgs<typename T::R> a = jobs[t.job];
-        march_tile<T, S, LAST, PPL, LDS, false, false>(a, t.strip, t.seg, t.seg & 1, lane,
+        march_tile<T, S, LAST, PPL, LDS, false, false, false>(a, t.strip, t.seg, t.seg & 1, lane,
                                                        &rings[LDS ? wave : 0].v[0][0][0][lane]);
     }
 }
@@ -813,11 +875,16 @@ march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
 // rings with 1 pair per lane, single only; time-dependent potentials
 // (periodic or closed): both rings, 1 pair per lane, at most kMaxTdSteps
 // steps per pass, single only.
-enum class Variant { Single, Batch, Closed, TimeDep, ClosedTimeDep };
+enum class Variant { Single, Batch, Closed, TimeDep, ClosedTimeDep, Order4 };
 
 template <class T, int S, bool LAST, int PPL, bool LDS, Variant V>
 const void* kernel_ptr() {
-    if constexpr (V == Variant::Single)
+    if constexpr (V == Variant::Order4) {
+        if constexpr (S == 5 && PPL == 1 && LDS)
+            return reinterpret_cast<const void*>(&march_kernel<T, 5, LAST, 1, true, false, false, true>);
+        else
+            return nullptr;
+    } else if constexpr (V == Variant::Single)
         return reinterpret_cast<const void*>(&march_kernel<T, S, LAST, PPL, LDS, false, false>);
     else if constexpr (V == Variant::Batch)
         return reinterpret_cast<const void*>(&march_batch_kernel<T, S, LAST, PPL, LDS>);
@@ -840,6 +907,8 @@ const void* pick_steps(int steps, std::integer_sequence<int, Ss...>) {
 
 template <class T, Variant V, bool LAST>
 const void* pick_variant(int steps, int ppl, bool lds) {
+    if constexpr (V == Variant::Order4)
+        return (steps == 5 && ppl == 1 && lds) ? kernel_ptr<T, 5, LAST, 1, true, V>() : nullptr;
     if (lds) {
         if (ppl != 1) return nullptr;
         // the time-dependent march evaluates a sine and cosine per site and

@@ -167,15 +167,30 @@ def test_time_dependent_potential_accepts_closed_meshes():
     (4, 3, 8, False),      # 2p m 4p m 4p m 2p: 1+1+1+1+1+1+1 = 7 -> split -> 8
     (2, 2, 6, False),      # 2p m 4p m 2p at S=2: 1+1+2+1+1 = 6 passes
 ])
-def test_pass_count_order4(S, steps, passes, copy):
-    h = tsq.tsq_plan_create(problem(order=4))
+def test_pass_count_order4_closed(S, steps, passes, copy):
+    """Closed meshes run fourth order as runs of second-order sub-steps."""
+    h = tsq.tsq_plan_create(problem(order=4, bc=1))
     try:
         tsq.tsq_plan_set_schedule(h, sched(S, 0, 0, 0))
         assert tsq.tsq_evolve_passes(h, steps) == (passes, copy)
         n4 = tsq.tsq_workspace_size(h)
-        h2 = tsq.tsq_plan_create(problem(order=2))
+        h2 = tsq.tsq_plan_create(problem(order=2, bc=1))
         assert n4 >= tsq.tsq_workspace_size(h2) + 64 * 32 * 16   # a second phase table
         tsq.tsq_plan_destroy(h2)
+    finally:
+        tsq.tsq_plan_destroy(h)
+
+
+@pytest.mark.parametrize("S", [1, 4, 6])
+@pytest.mark.parametrize("steps,passes,copy", [(1, 1, True), (2, 2, False), (7, 7, True),
+                                               (200, 200, False), (0, 0, False)])
+def test_pass_count_order4_periodic(S, steps, passes, copy):
+    """Periodic 2D meshes fuse the five sub-steps of a fourth-order step into one
+    pass, whatever the schedule's steps per pass; an odd count ends with a copy."""
+    h = tsq.tsq_plan_create(problem(order=4))
+    try:
+        tsq.tsq_plan_set_schedule(h, sched(S, 0, 0, 0))
+        assert tsq.tsq_evolve_passes(h, steps) == (passes, copy)
     finally:
         tsq.tsq_plan_destroy(h)
 
