@@ -247,6 +247,8 @@ def run_td(dtype: str, p, psi0, V0, W, f, args, bc: str = "periodic"):
     import torch
     import paper_1208_2407_amd as tsq
 
+    from paper_1208_2407_amd import autotune
+
     tdt = torch.complex128 if dtype == "c128" else torch.complex64
     psi = psi0.to(tdt).contiguous()
     plan = tsq.Plan(p.nx, p.ny, p.dt, dtype, bc=bc, device=psi.device)
@@ -254,23 +256,7 @@ def run_td(dtype: str, p, psi0, V0, W, f, args, bc: str = "periodic"):
     if args.schedule:
         plan.set_schedule(*[int(v) for v in args.schedule.split(",")])
     else:
-        scratch = psi.clone()
-        best = None
-        for cand in [(S, 0, 1, st) for S in (1, 2, 3, 4) for st in (1, 2)]:
-            plan.set_schedule(*cand)
-            plan.evolve_td(scratch, f[:8])
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            plan.evolve_td(scratch, f[:120])
-            e1.record()
-            e1.synchronize()
-            ms = e0.elapsed_time(e1)
-            if args.verbose:
-                log(f"td {dtype} S={cand[0]} store={cand[3]}: {ms:.3f} ms / 120 steps")
-            if best is None or ms < best[0]:
-                best = (ms, cand)
-        plan.set_schedule(*best[1])
-        del scratch
+        autotune.tune_td(plan, psi, f[:120], log=log if args.verbose else None)
     sched = plan.schedule()
     passes, copy_back = plan.passes(len(f))
     V_end = V0 + float(f[-1]) * W   # potential at the last step's midpoint, for the energy
@@ -308,7 +294,8 @@ def run_td(dtype: str, p, psi0, V0, W, f, args, bc: str = "periodic"):
         "value": site_steps / wall, "ms_per_step": wall / args.steps * 1e3,
         "schedule": {"steps_per_pass": sched[0], "pairs_per_lane": sched[2],
                      "phase_store": {1: "registers", 2: "lds"}[sched[3]],
-                     "passes_per_solve": passes, "copy_back": copy_back},
+                     "passes_per_solve": passes, "copy_back": copy_back,
+                     "picked_by": "given" if args.schedule else "autotune.tune_td"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_launch": alg_bytes,

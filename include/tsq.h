@@ -192,7 +192,7 @@ int tsq_evolve(tsq_plan* plan, void* psi_dev, int64_t steps, void* ws, size_t ws
  * midpoint, V0 + f_n W with f_n = f(t_n + dt/2), which keeps the product second
  * order for smooth f.  Order-2 plans of 2D meshes (periodic or closed); every step's phase factor
  * exp(-i dt (V0 + f_n W + eps0) / hbar) is formed in FP64 inside the march, so
- * up to 4 steps fuse per pass (a plan scheduled deeper runs 4). */
+ * up to 6 steps fuse per pass (a plan scheduled deeper runs 6). */
 
 /* Store the time-dependent table of V0_dev and W_dev (device, nx*ny doubles
  * each) in `ws`: per site dt (V0 + eps0) / hbar and dt W / hbar (16 bytes, the

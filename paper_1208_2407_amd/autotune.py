@@ -156,6 +156,64 @@ def tune(plan, psi, *, candidates: Optional[Iterable[Schedule]] = None, steps: i
     return best, table
 
 
+# ---------------------------------------------------------------- time-dependent potential
+
+# steps per pass (the time-dependent march fuses at most 6) x phase store
+TD_CANDIDATES: List[Schedule] = [(S, 0, 1, store) for S in (1, 2, 3, 4, 5, 6) for store in (1, 2)]
+
+
+def time_schedule_td(plan, psi, f, schedule: Schedule, repeats: int = 2) -> float:
+    """Best-of-`repeats` milliseconds of plan.evolve_td(psi, f) under `schedule`."""
+    import torch
+    plan.set_schedule(*schedule)
+    plan.evolve_td(psi, f[: 2 * schedule[0]])  # warm the code path
+    best = float("inf")
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.evolve_td(psi, f)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def tune_td(plan, psi, f, *, candidates: Optional[Iterable[Schedule]] = None, steps: int = 120,
+            use_cache: bool = True, log=None) -> Tuple[Schedule, Dict[str, float]]:
+    """Pick the fastest schedule for a plan holding a time-dependent table
+    (tsq_set_potential_td) and set it: times `steps` steps of the modulation `f`
+    (repeated if shorter) on a scratch copy of `psi` under each candidate; cached
+    per device, dtype, mesh, boundary and library, apart from the static choice."""
+    import numpy as np
+    import torch
+    arch = torch.cuda.get_device_properties(psi.device).gcnArchName.split(":")[0]
+    key = _key(arch, plan.dtype, plan.problem.nx, plan.problem.ny, plan.problem.order,
+               plan.problem.bc) + "|td"
+    db = _load() if use_cache else {}
+    if use_cache and key in db and len(db[key].get("schedule", [])) == 4:
+        sched = tuple(db[key]["schedule"])
+        plan.set_schedule(*sched)
+        return sched, db[key].get("table", {})
+    fs = np.resize(np.asarray(f, dtype=np.float64), steps)
+    scratch = psi.clone()
+    table: Dict[str, float] = {}
+    timed: List[Tuple[float, Schedule]] = []
+    for cand in (candidates or TD_CANDIDATES):
+        ms = time_schedule_td(plan, scratch, fs, cand)
+        table[",".join(map(str, cand))] = ms
+        timed.append((ms, tuple(cand)))
+        if log:
+            log(f"autotune {key} S={cand[0]} store={cand[3]}: {ms:.3f} ms")
+    best = pick(timed)
+    del scratch
+    plan.set_schedule(*best)
+    if use_cache:
+        db[key] = {"schedule": list(best), "table": table, "steps": steps}
+        _store(db)
+    return best, table
+
+
 # ---------------------------------------------------------------- batched form
 
 # steps per pass x phase store (one pair per lane), then the tile height

@@ -39,7 +39,7 @@ struct tsq_plan {
     SubStep kind[2];
     tsq_schedule sched;   // resolved (segment_rows may stay 0 = per launch)
     size_t sites, elem, pelem;
-    size_t off_psi2, off_ptab, off_scratch, ws_bytes;
+    size_t off_psi2, off_ptab, off_scratch, off_turns, ws_bytes;
     const void* ws_bound;
     bool td;  // the bound workspace holds a time-dependent table (tsq_set_potential_td)
 };
@@ -707,7 +707,9 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
         end = align_up(end + p->sites * p->pelem, 256);
     }
     p->off_scratch = end;
-    p->ws_bytes = p->off_scratch + kScratchBytes;
+    // the time-dependent phase's kTurns factors (double2)
+    p->off_turns = align_up(p->off_scratch + kScratchBytes, 256);
+    p->ws_bytes = p->off_turns + tsq::kTurns * 16;
     p->ws_bound = nullptr;
     p->td = false;
     *out = p;
@@ -815,9 +817,11 @@ int tsq_set_potential_td(tsq_plan* plan, const double* V0, const double* W, void
     int rc = check_ws(plan, ws, ws_bytes);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
-    hipError_t e = tsq::launch_td_table(V0, W, w + plan->kind[0].off_ptab, (long long)plan->sites,
-                                        plan->kind[0].dt, plan->eps0, plan->p.hbar,
-                                        static_cast<hipStream_t>(stream));
+    // periodic meshes: the factors carry a step's cosines, as the static table does
+    const double scale = std::exp(-0.5 * table_log(plan, 0));
+    hipError_t e = tsq::launch_td_table(V0, W, w + plan->kind[0].off_ptab, w + plan->off_turns,
+                                        (long long)plan->sites, plan->kind[0].dt, plan->eps0,
+                                        plan->p.hbar, scale, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "table launch: %s", hipGetErrorString(e));
     plan->ws_bound = ws;
     plan->td = true;
@@ -909,6 +913,7 @@ int run_evolution(tsq_plan* plan, void* psi, int64_t steps, void* ws, hipStream_
     d.phase_lds = lds;
     d.closed = plan->p.bc == TSQ_BC_CLOSED;
     d.td = td;
+    d.ptab2 = td ? w + plan->off_turns : nullptr;
     int64_t i = 0, n0 = 0;  // pass index, first step of the pass
     for (const PassGroup& g : groups) {
         const SubStep& u = plan->kind[g.kind];

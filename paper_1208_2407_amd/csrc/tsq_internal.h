@@ -39,7 +39,7 @@ struct PassDesc {
     // fourth order in one pass per step (periodic): sub-steps p, p, m, p, p;
     // the fields above are those of the p sub-step, these of the m sub-step
     bool u4 = false;
-    const void* ptab2 = nullptr;  // phase table of the m sub-step
+    const void* ptab2 = nullptr;  // phase table of the m sub-step; td: the kTurns factors
     Coef64 mxh, myh;              // m sub-step, tau = its dt / 2
     double log_table_p = 0.0, log_table_m = 0.0;  // -2 log of each table's scale
 };
@@ -47,7 +47,8 @@ struct PassDesc {
 constexpr int kMaxSteps = 8;     // deepest fusion (phase ring in LDS)
 constexpr int kMaxRegSteps = 6;  // deepest fusion with the phase ring in registers
 constexpr int kMaxRegSteps2 = 4; // ... with two x-pairs per lane
-constexpr int kMaxTdSteps = 4;   // deepest fusion with a time-dependent potential
+constexpr int kMaxTdSteps = 6;   // deepest fusion with a time-dependent potential
+constexpr int kTurns = 256;      // time-dependent phase: factors exp(-i j pi/128), j mod 256
 constexpr int kWaveSize = 64;
 constexpr int kWavesPerBlock = 4;
 
@@ -102,7 +103,7 @@ struct MarchArgs {
     const void* src;
     void* dst;
     const void* ptab;
-    const void* ptab2;  // fourth order: the m sub-step's table
+    const void* ptab2;  // fourth order: the m sub-step's table; time-dependent: the kTurns factors
     int nx, ny, strip_sites, seg_rows, nstrips, nsegs;
     R o1xs, o1xd, o1ys, o1yd;  // odd factors opening the pass: tau = dt/2 (first pass) or dt
     R o2xs, o2xd, o2ys, o2yd;  // odd factors between steps, tau = dt
@@ -172,22 +173,17 @@ MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
         a.o1yd = a.o2yd = a.c1yd = a.ehxd = a.ehyd = R(0);
         // closing stage: odd x and y at dt/2, no table
         delta_odd_x<R>(d.oxh.al, log_sec2(a.c1ys), a.c1xs, a.c1xd);
-        if (d.td) {
-            // every stage's odd x factor restores that stage's cosines
-            delta_odd_x<R>(ox1.al, Le + log_sec2(a.o1ys), a.o1xs, a.o1xd);
-            delta_odd_x<R>(d.ox2.al, Le + log_sec2(a.o2ys), a.o2xs, a.o2xd);
+        // the phase factor (table or, time-dependent, the turns) restores a
+        // steady step's cosines (L_step); stage 0 of the first pass restores
+        // the rest of its own
+        a.o2xs = tangent<R>(d.ox2);
+        a.o2xd = R(0);
+        if (d.first) {
+            const double L_step = step_log_sec2<R>(d.oxh, d.oyh, d.ox2, d.oy2);
+            delta_odd_x<R>(ox1.al, Le + log_sec2(a.o1ys) - L_step, a.o1xs, a.o1xd);
         } else {
-            // the table restores a steady step's cosines (L_step); stage 0 of the
-            // first pass restores the rest of its own
-            a.o2xs = tangent<R>(d.ox2);
-            a.o2xd = R(0);
-            if (d.first) {
-                const double L_step = step_log_sec2<R>(d.oxh, d.oyh, d.ox2, d.oy2);
-                delta_odd_x<R>(ox1.al, Le + log_sec2(a.o1ys) - L_step, a.o1xs, a.o1xd);
-            } else {
-                a.o1xs = a.o2xs;
-                a.o1xd = R(0);
-            }
+            a.o1xs = a.o2xs;
+            a.o1xd = R(0);
         }
     }
     for (int k = 0; k < kMaxSteps; ++k) a.g[k] = (d.td && d.f && k < d.steps) ? d.f[k] : 0.0;
@@ -242,8 +238,11 @@ hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long 
 // Table of the time-dependent potential V0 + f(t) W: per site the phase angle
 // theta0 = dt (V0 + eps0) / hbar and its modulation w = dt W / hbar, as a
 // double2 (16 B/site, both dtypes); step n's phase is exp(-i (theta0 + f_n w)).
-hipError_t launch_td_table(const double* V0, const double* W, void* table, long long sites,
-                           double dt, double eps0, double hbar, hipStream_t s);
+// `turns` receives the kTurns factors scale * exp(-i j pi/128) (double2) the
+// march composes each step's factor from.
+hipError_t launch_td_table(const double* V0, const double* W, void* table, void* turns,
+                           long long sites, double dt, double eps0, double hbar, double scale,
+                           hipStream_t s);
 hipError_t launch_pass(int dtype, const PassDesc& d, hipStream_t s);
 // Second stage of the FP64 reductions: sum the `nblocks` (norm, energy) partials
 // in a fixed order into result[0] = norm, result[1] = energy / norm.

@@ -111,79 +111,57 @@ __device__ __forceinline__ void apply_phase(float& re, float& im, const float4 p
 
 // ------------------------------------------------------------------ time-dependent phase
 
-// sin and cos of x in FP64 for the phase of a time-dependent potential,
-// written from the mathematics: Cody and Waite's additive reduction
-// r = x - k pi/2, with pi/2 split into C1 (the double nearest pi/2) and C2
-// (the double nearest pi/2 - C1) and the product k C1 exact inside an FMA;
-// the Taylor series of sin and cos on |r| <= pi/4; the quadrant k mod 4.
-// k comes from adding 1.5 * 2^52 inside the FMA that forms x * 2/pi: the sum
-// then holds round(x * 2/pi) in the low bits of its significand (|x| < 2^50),
-// and the quadrant's sign is one exclusive or on the sign bit.
-// FULL: series through r^17 and r^16 (first omitted terms below 1e-19; a few
-// ulp for |x| < 2^40), for complex128.  Otherwise through r^13 and r^14 (first
-// omitted terms below 2.1e-14 and 1.1e-15), for complex64, whose state keeps
-// 24 bits.
+// Phase factor of step n under V0 + f_n W, g * exp(-i x) with x = theta0 + f_n w
+// (tw = (theta0, w) of the site, f = f_n), in FP64, by angle addition:
+// x = j pi/128 + r with j the integer nearest x * 128/pi and |r| <= pi/256,
+// exp(-i x) = exp(-i j pi/128) exp(-i r).  `turns` holds the 256 factors
+// g exp(-i j pi/128), j mod 256 (g is the cosine restoration of a periodic
+// mesh's tangent form, 1 between walls); exp(-i r) comes from the Taylor
+// series of cos and sin on the small interval.  The factor is a function of
+// (theta0, w, f_n) alone, so every schedule forms the same bits.
+// Reduction (Cody and Waite): pi/128 split into C1 (the double nearest) and
+// C2 (the double nearest pi/128 - C1), the product j C1 exact inside an FMA;
+// j comes from adding 1.5 * 2^52 inside the FMA that forms x * 128/pi, after
+// which the low bits of the sum's significand hold j (|x| < 2^45).
+// FULL (complex128): sin r through r^5, cos r through r^6 (first omitted terms
+// below 1e-17 and 1e-19).  Otherwise (complex64, whose state keeps 24 bits):
+// sin r through r^3, cos r through r^4 (below 2.4e-12 and 5e-15).
 template <bool FULL>
-__device__ __forceinline__ void sincos_td(double x, double& sn, double& cs) {
-    const double C1 = 0x1.921fb54442d18p+0;   // pi/2 rounded to double
-    const double C2 = 0x1.1a62633145c07p-54;  // pi/2 - C1 rounded to double
+__device__ __forceinline__ double2 td_factor(const double2 tw, double f, const double2* turns) {
+    const double C1 = 0x1.921fb54442d18p-6;   // pi/128 rounded to double
+    const double C2 = 0x1.1a62633145c07p-60;  // pi/128 - C1 rounded to double
     const double shifter = 0x1.8p52;          // 1.5 * 2^52: unit in the last place 1
-    const double t = mad(x, 0x1.45f306dc9c883p-1, shifter);  // x * (2/pi) + shifter
-    const double k = t - shifter;                              // exact
-    const unsigned q = (unsigned)__double2loint(t);           // k mod 4 in bits 0..1
-    double r = mad(-k, C1, x);
-    r = mad(-k, C2, r);
+    const double x = mad(f, tw.y, tw.x);
+    const double t = mad(x, 0x1.45f306dc9c883p+5, shifter);  // x * (128/pi) + shifter
+    const double j = t - shifter;                              // exact
+    const unsigned idx = (unsigned)__double2loint(t) & 255u;   // j mod 256
+    double r = mad(-j, C1, x);
+    r = mad(-j, C2, r);
     const double r2 = r * r;
-    // sin r = r + r^3 (-1/3! + r^2/5! - ...), cos r = 1 + r^2 (-1/2! + r^2/4! - ...)
-    double ps, pc;
+    double ps = -1.0 / 6.0, pc = 1.0 / 24.0;
     if constexpr (FULL) {
-        ps = 1.0 / 355687428096000.0;                  // 1/17!
-        ps = mad(ps, r2, -1.0 / 1307674368000.0);     // 1/15!
-        ps = mad(ps, r2, 1.0 / 6227020800.0);         // 1/13!
-        pc = 1.0 / 20922789888000.0;                   // 1/16!
-        pc = mad(pc, r2, -1.0 / 87178291200.0);       // 1/14!
-    } else {
-        ps = 1.0 / 6227020800.0;
-        pc = -1.0 / 87178291200.0;
+        ps = mad(r2, 1.0 / 120.0, ps);
+        pc = mad(r2, -1.0 / 720.0, pc);
     }
-    ps = mad(ps, r2, -1.0 / 39916800.0);   // 1/11!
-    ps = mad(ps, r2, 1.0 / 362880.0);      // 1/9!
-    ps = mad(ps, r2, -1.0 / 5040.0);       // 1/7!
-    ps = mad(ps, r2, 1.0 / 120.0);         // 1/5!
-    ps = mad(ps, r2, -1.0 / 6.0);          // 1/3!
-    const double sr = mad(r * r2, ps, r);
-    pc = mad(pc, r2, 1.0 / 479001600.0);   // 1/12!
-    pc = mad(pc, r2, -1.0 / 3628800.0);    // 1/10!
-    pc = mad(pc, r2, 1.0 / 40320.0);       // 1/8!
-    pc = mad(pc, r2, -1.0 / 720.0);        // 1/6!
-    pc = mad(pc, r2, 1.0 / 24.0);          // 1/4!
-    pc = mad(pc, r2, -0.5);                // 1/2!
-    const double cr = mad(r2, pc, 1.0);
-    // (sin, cos) of x = (sr, cr), (cr, -sr), (-sr, -cr), (-cr, sr) for q = 0..3:
-    // swap on odd q; sin negative for q = 2, 3, cos for q = 1, 2
-    const bool odd = (q & 1u) != 0;
-    const double a = odd ? cr : sr;
-    const double b = odd ? sr : cr;
-    const int ssign = (int)((q << 30) & 0x80000000u);
-    const int csign = (int)(((q + 1u) << 30) & 0x80000000u);
-    sn = __hiloint2double(__double2hiint(a) ^ ssign, __double2loint(a));
-    cs = __hiloint2double(__double2hiint(b) ^ csign, __double2loint(b));
+    const double sr = mad(r * r2, ps, r);          // sin r
+    const double cr = mad(r2, mad(r2, pc, -0.5), 1.0);  // cos r
+    const double2 u = turns[idx];                  // g exp(-i j pi/128)
+    // (u.x + i u.y)(cr - i sr)
+    return make_double2(mad(u.x, cr, u.y * sr), mad(u.y, cr, -(u.x * sr)));
 }
 
-// Potential phase of step n under V0 + f_n W: tw = (theta0, w) of the site,
-// g = f_n; the factor exp(-i (theta0 + g w)) is formed in FP64 and applied in
-// FP64 (complex64: to the state widened to FP64, the product rounded once).
-__device__ __forceinline__ void apply_phase_td(double& re, double& im, const double2 tw, double g) {
-    double sn, cs;
-    sincos_td<true>(mad(g, tw.y, tw.x), sn, cs);
-    apply_phase(re, im, make_double2(cs, -sn));
+// Apply the factor: complex128 in place; complex64 widened to FP64,
+// multiplied, rounded once.
+__device__ __forceinline__ void apply_phase_td(double& re, double& im, const double2 tw, double f,
+                                               const double2* turns) {
+    apply_phase(re, im, td_factor<true>(tw, f, turns));
 }
-__device__ __forceinline__ void apply_phase_td(float& re, float& im, const double2 tw, double g) {
-    double sn, cs;
-    sincos_td<false>(mad(g, tw.y, tw.x), sn, cs);
+__device__ __forceinline__ void apply_phase_td(float& re, float& im, const double2 tw, double f,
+                                               const double2* turns) {
+    const double2 p = td_factor<false>(tw, f, turns);
     const double r = re, i = im;
-    re = (float)mad(r, cs, i * sn);    // (r + i i)(cs - i sn)
-    im = (float)mad(i, cs, -(r * sn));
+    re = (float)mad(r, p.x, -(i * p.y));
+    im = (float)mad(r, p.y, i * p.x);
 }
 
 // ------------------------------------------------------------------ dtype traits
@@ -357,9 +335,10 @@ __device__ __forceinline__ void phase_row(Row<R, SPL>& w, const PT* p) {
 }
 
 template <class R, int SPL>
-__device__ __forceinline__ void phase_row_td(Row<R, SPL>& w, const double2* p, double g) {
+__device__ __forceinline__ void phase_row_td(Row<R, SPL>& w, const double2* p, double f,
+                                             const double2* turns) {
 #pragma unroll
-    for (int i = 0; i < SPL; ++i) apply_phase_td(w.re[i], w.im[i], p[i], g);
+    for (int i = 0; i < SPL; ++i) apply_phase_td(w.re[i], w.im[i], p[i], f, turns);
 }
 
 // Calls f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
@@ -415,17 +394,17 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // k+1's even factors and the potential phase on o.  Stage K-1 = S of the
 // last pass applies only the closing odd factors.  With a time-dependent
 // potential (TD) the phase pair holds (theta0, w) per site and stage k forms
-// step k's factor from a.g[k].  Closed meshes rotate the y-pairs that cross
-// a wall with zero coefficients (`qk` is the pair stage k completes; a
-// wavefront-uniform test) and apply every factor in the delta form; periodic
-// meshes apply the tangent form, the odd x factors of stage 0 and of the
-// closing stage (and of every stage under a time-dependent potential) in the
-// delta form that restores the cosines (see MarchArgs).
+// step k's factor from a.g[k] and `turns` (LDS).  Closed meshes rotate the
+// y-pairs that cross a wall with zero coefficients (`qk` is the pair stage k
+// completes; a wavefront-uniform test) and apply every factor in the delta
+// form; periodic meshes apply the tangent form, the odd x factors of stage 0
+// and of the closing stage in the delta form that restores the cosines the
+// phase factor does not (see MarchArgs).
 template <int S, int K, bool CLOSED, bool TD, bool U4, class R, int SPL, class PT, class PhaseFn>
 __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
                                                const MarchArgs<R>& a,
                                                const XPairs<SPL / 2, CLOSED>& xm, int qk, bool rev,
-                                               PhaseFn&& phase) {
+                                               const double2* turns, PhaseFn&& phase) {
     if constexpr (U4) {
         // one fourth-order step: sub-steps p, p, m, p, p (Eq. "fourthorder");
         // stage k's odd x factor (delta form) carries its own cosines over
@@ -459,7 +438,7 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
     }
     if constexpr (!CLOSED) {
         (void)oyd; (void)qk; (void)rev;
-        if (TD || k == 0 || k == S) {
+        if (k == 0 || k == S) {
             odd_x<false>(o.g, oxs, oxd, xm);
             odd_x<false>(n.f, oxs, oxd, xm);
         } else {
@@ -473,8 +452,8 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
             even_x_t(o.g, a.ehxs);
             pair_y_t(o.f, o.g, a.ehys);
             if constexpr (TD) {
-                phase_row_td(o.f, ph.f, a.g[k]);
-                phase_row_td(o.g, ph.g, a.g[k]);
+                phase_row_td(o.f, ph.f, a.g[k], turns);
+                phase_row_td(o.g, ph.g, a.g[k], turns);
             } else {
                 phase_row(o.f, ph.f);
                 phase_row(o.g, ph.g);
@@ -500,8 +479,8 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
         const R eys = ey_ok ? a.ehys : R(0), eyd = ey_ok ? a.ehyd : R(0);
         pair_y(o.f, o.g, eys, eyd);
         if constexpr (TD) {
-            phase_row_td(o.f, ph.f, a.g[k]);
-            phase_row_td(o.g, ph.g, a.g[k]);
+            phase_row_td(o.f, ph.f, a.g[k], turns);
+            phase_row_td(o.g, ph.g, a.g[k], turns);
         } else {
             phase_row(o.f, ph.f);
             phase_row(o.g, ph.g);
@@ -575,7 +554,8 @@ using TableT = std::conditional_t<TD, double2, typename T::TT>;
 
 template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD, bool U4>
 __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, int strip, int seg,
-                                           bool rev, int lane, PhaseT<T, TD>* ring) {
+                                           bool rev, int lane, PhaseT<T, TD>* ring,
+                                           const double2* turns) {
     using R = typename T::R;
     using PT = PhaseT<T, TD>;
     constexpr int SPL = 2 * PPL;
@@ -784,7 +764,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
             if (it > 2 * k)
             pipeline_stage<S, K, CLOSED, TD, U4, R, SPL, PT>(
                 k, home[(u - 1 - k + 2 * NH) % NH], home[(u - k + 2 * NH) % NH], a, xm,
-                rev ? q + k : q - k, rev, [&](int kk) {
+                rev ? q + k : q - k, rev, turns, [&](int kk) {
                     if (U4 && kk == 2) return phm[U4 ? u % 2 : 0];
                     if (!LDS || kk == 0) return ph[(u - 1 - kk + 2 * NP) % NP];
                     int slot = wslot - kk;
@@ -827,27 +807,35 @@ template <class T, int S, bool LAST, int PPL, bool LDS, bool CLOSED, bool TD, bo
 __global__ void __launch_bounds__(kWaveSize * kWavesPerBlock)
 march_kernel(const MarchArgs<typename T::R> a) {
     __shared__ WaveRing<PhaseT<T, TD>, S, PPL, LDS> rings[LDS ? kWavesPerBlock : 1];
+    __shared__ double2 turns[TD ? kTurns : 1];
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
     // XCD-aware block order: blocks are dealt round-robin to the 8 XCDs, so
-    // block b runs on XCD b % 8; give each XCD a contiguous run of tiles so
-    // the halo rows shared by neighbouring segments meet in one L2.  A block
-    // marches one segment of kWavesPerBlock neighbouring strips (one per
-    // wavefront): the halo columns two strips share are read by two
-    // wavefronts of one compute unit at about the same time, so the second
-    // read hits the cache.
+    // block b runs on XCD b % 8; give each XCD a contiguous run of tiles, in
+    // segment-major order, so the halo columns neighbouring strip groups of
+    // one band of rows share (2K lanes of every 64, the larger halo) are read
+    // at about the same time through one L2.  A block marches one segment of
+    // kWavesPerBlock neighbouring strips (one per wavefront): the halo columns
+    // two of its strips share are read by two wavefronts of one compute unit
+    // at about the same time, so the second read hits the cache.
     const int nb = gridDim.x;
     const int full = nb & ~7;
     const int b = blockIdx.x;
     const int lb = (b < full) ? ((b & 7) * (full >> 3) + (b >> 3)) : b;
     const int ngroups = (a.nstrips + kWavesPerBlock - 1) / kWavesPerBlock;
     if (lb >= ngroups * a.nsegs) return;  // uniform per block
-    const int grp = lb / a.nsegs;
-    const int seg = lb - grp * a.nsegs;
+    if constexpr (TD) {
+        // the time-dependent phase's table of 256 factors, one per thread
+        static_assert(kTurns == kWaveSize * kWavesPerBlock, "one table entry per thread");
+        turns[threadIdx.x] = reinterpret_cast<const double2*>(a.ptab2)[threadIdx.x];
+        __syncthreads();
+    }
+    const int seg = lb / ngroups;
+    const int grp = lb - seg * ngroups;
     const int strip = grp * kWavesPerBlock + wave;
     if (strip >= a.nstrips) return;  // uniform per wavefront
     march_tile<T, S, LAST, PPL, LDS, CLOSED, TD, U4>(a, strip, seg, seg & 1, lane,
-                                                 &rings[LDS ? wave : 0].v[0][0][0][lane]);
+                                                 &rings[LDS ? wave : 0].v[0][0][0][lane], turns);
 }
 
 // Many problems: a fixed grid of wavefronts walks a work list of tiles
@@ -865,7 +853,8 @@ march_batch_kernel(const MarchArgs<typename T::R>* __restrict__ jobs,
         const BatchTile t = tiles[i];
         const MarchArgs<typename T::R> a = jobs[t.job];
         march_tile<T, S, LAST, PPL, LDS, false, false, false>(a, t.strip, t.seg, t.seg & 1, lane,
-                                                       &rings[LDS ? wave : 0].v[0][0][0][lane]);
+                                                       &rings[LDS ? wave : 0].v[0][0][0][lane],
+                                                       nullptr);
     }
 }
 
@@ -911,8 +900,8 @@ const void* pick_variant(int steps, int ppl, bool lds) {
         return (steps == 5 && ppl == 1 && lds) ? kernel_ptr<T, 5, LAST, 1, true, V>() : nullptr;
     if (lds) {
         if (ppl != 1) return nullptr;
-        // the time-dependent march evaluates a sine and cosine per site and
-        // step; beyond 4 steps per pass its loop outgrows the instruction cache
+        // the time-dependent march forms a phase factor per site and step;
+        // beyond 6 steps per pass its loop outgrows the instruction cache
         if constexpr (V == Variant::TimeDep || V == Variant::ClosedTimeDep)
             return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxTdSteps>());
         return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxSteps>());

@@ -64,6 +64,16 @@ __global__ void td_table(const double* __restrict__ V0, const double* __restrict
         T[l] = make_double2(dt * (V0[l] + eps0) / hbar, dt * W[l] / hbar);
 }
 
+// The march's factors scale * exp(-i j pi/128), j = 0 .. kTurns-1 (j / 128 is
+// exact, so sincospi sees the angle without rounding).
+__global__ void td_turns(double2* __restrict__ U, double scale) {
+    const int j = threadIdx.x;
+    if (j >= kTurns) return;
+    double sn, cs;
+    sincospi((double)j / 128.0, &sn, &cs);
+    U[j] = make_double2(scale * cs, -(scale * sn));
+}
+
 // ------------------------------------------------------------------ norm and energy (Sec. 2)
 
 __device__ __forceinline__ void load_site(const void* psi, long long l, double& re, double& im, C128) {
@@ -209,13 +219,18 @@ hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long 
     return hipGetLastError();
 }
 
-hipError_t launch_td_table(const double* V0, const double* W, void* table, long long sites,
-                           double dt, double eps0, double hbar, hipStream_t s) {
+hipError_t launch_td_table(const double* V0, const double* W, void* table, void* turns,
+                           long long sites, double dt, double eps0, double hbar, double scale,
+                           hipStream_t s) {
     const int threads = 256;
     long long want = (sites + threads - 1) / threads;
     const int blocks = (int)(want < 8192 ? want : 8192);
     hipLaunchKernelGGL(td_table, dim3(blocks), dim3(threads), 0, s, V0, W,
                        reinterpret_cast<double2*>(table), sites, dt, eps0, hbar);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(td_turns, dim3(1), dim3(kTurns), 0, s, reinterpret_cast<double2*>(turns),
+                       scale);
     return hipGetLastError();
 }
 

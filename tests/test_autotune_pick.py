@@ -22,3 +22,10 @@ def test_pick_tie_bound():
     t = 2.0
     assert pick([(t * (1 + TIE) * 1.001, (3, 0, 1, 1)), (t, (4, 0, 1, 1))]) == (4, 0, 1, 1)
     assert pick([(t * (1 + TIE) * 0.999, (3, 0, 1, 1)), (t, (4, 0, 1, 1))]) == (3, 0, 1, 1)
+
+
+def test_td_candidates_stay_within_the_time_dependent_march():
+    from paper_1208_2407_amd.autotune import TD_CANDIDATES
+    assert {c[0] for c in TD_CANDIDATES} == {1, 2, 3, 4, 5, 6}
+    assert {c[3] for c in TD_CANDIDATES} == {1, 2}
+    assert all(c[1] == 0 and c[2] == 1 for c in TD_CANDIDATES)

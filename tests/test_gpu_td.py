@@ -39,7 +39,7 @@ SHAPES = [(2, 2), (4, 6), (130, 66), (258, 300), (66, 1030)]
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("S", [1, 2, 3, 4])
+@pytest.mark.parametrize("S", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_td_ragged_meshes(shape, S, dtype):
     nx, ny = shape
@@ -60,7 +60,7 @@ CLOSED_SHAPES = [(2, 2), (3, 5), (131, 67), (257, 301)]
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("S", [1, 3, 4])
+@pytest.mark.parametrize("S", [1, 3, 4, 6])
 @pytest.mark.parametrize("shape", CLOSED_SHAPES)
 def test_td_closed_meshes(shape, S, dtype):
     """The time-dependent potential between hard walls (odd sides allowed) against the
@@ -113,7 +113,7 @@ def test_td_closed_constant_modulation_equals_static_potential(dtype):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_td_schedule_and_call_split_do_not_change_a_bit(dtype):
     """Every schedule gives the same bits (a schedule deeper than the
-    time-dependent march fuses runs 4).  Splitting the modulation over several
+    time-dependent march fuses runs 6).  Splitting the modulation over several
     calls continues the evolution: each call closes and reopens the odd half
     factors that one call merges, so the split agrees to rounding."""
     nx, ny = 258, 130
@@ -198,6 +198,30 @@ def test_td_driven_mesh_1024(dtype):
     assert err <= TOL[dtype]
 
 
+@pytest.mark.parametrize("bc", ["periodic", "closed"])
+def test_td_tuner_picks_a_candidate_and_keeps_the_bits(bc):
+    """autotune.tune_td times the candidates on a scratch copy, sets its choice on the
+    plan and leaves the state alone; the tuned evolution equals the one-step-per-pass one."""
+    from paper_1208_2407_amd import autotune
+    nx, ny = 256, 130
+    psi0 = wl.random_state(nx, ny, 31)
+    V0 = wl.random_potential(nx, ny, 32)
+    W = wl.random_potential(nx, ny, 33)
+    f = np.random.default_rng(34).uniform(-1, 1, 23)
+    psi = torch.from_numpy(psi0).to(torch.complex64).cuda()
+    plan = tsq.Plan(nx, ny, 0.07, "c64", bc=bc, device=psi.device)
+    plan.set_potential_td(torch.from_numpy(V0).cuda(), torch.from_numpy(W).cuda())
+    before = psi.clone()
+    sched, table = autotune.tune_td(plan, psi, f, steps=24, use_cache=False)
+    assert torch.equal(psi, before)
+    assert sched in autotune.TD_CANDIDATES and plan.schedule() == sched
+    assert len(table) == len(autotune.TD_CANDIDATES)
+    plan.evolve_td(psi, f)
+    torch.cuda.synchronize()
+    ref = gpu_evolve_td(psi0, V0, W, f, 0.07, "c64", steps_per_pass=1, bc=bc)
+    assert np.array_equal(psi.cpu().numpy().astype(np.complex128), ref)
+
+
 def test_td_state_errors():
     nx, ny = 64, 32
     plan = tsq.Plan(nx, ny, 0.1, "c128")
@@ -222,14 +246,15 @@ def test_td_state_errors():
         plan.evolve_td(psi, [0.1])
     assert ei.value.status == -1
     plan.set_schedule(8, 0, 1, 2)
-    assert plan.passes(8) == (2, False)   # runs 4 steps per pass
+    assert plan.passes(8) == (2, False)   # runs 6 steps per pass, then 2
+    assert plan.passes(12) == (2, False)
 
 
 @pytest.mark.parametrize("bc", ["periodic", "closed"])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_td4096_sampled_windows(dtype, bc):
     """The 4096^2 driven workload (packets and bumps under the shaken standing wave)
-    at full size in the schedules its tuner picks among (3 and 4 steps per pass, both
+    at full size in the schedules its tuner picks among (4, 5 and 6 steps per pass, both
     phase rings; all bitwise equal), 50 steps; 256^2 windows on the packets and at the
     mesh corner (and, between walls, along an edge) against oracle runs on the window
     plus its light cone."""
@@ -241,7 +266,7 @@ def test_td4096_sampled_windows(dtype, bc):
     W = wl.standing_wave(p).numpy()
     f = wl.drive(p.dt, p.steps)
     runs = [gpu_evolve_td(psi0, V0, W, f, p.dt, dtype, steps_per_pass=S, phase_store=st, bc=bc)
-            for S in (3, 4) for st in (1, 2)]
+            for S in (4, 5, 6) for st in (1, 2)]
     for r in runs[1:]:
         assert np.array_equal(r, runs[0])
     h = w = 256
