@@ -540,13 +540,18 @@ __device__ __forceinline__ PT zero_phase() {
 //
 // Register homes: the row pair that enters the pipeline in iteration j lives
 // in home j mod NH until it is stored K iterations later; stage k of
-// iteration j works on homes j-1-k (older) and j-k (newer), and the pair for
-// iteration j+1 is loaded into home j+1 meanwhile, so NH = K+2 homes suffice
-// and the march loop, unrolled by NH, moves no data between registers.
-// Phases: the phase rows of pair j are loaded in iteration j and first used
-// by stage 0 in iteration j+1; register phases keep one home per psi home,
-// the LDS ring keeps two register homes (pairs j and j-1) and moves pair
-// j-1's phase to the ring at the end of iteration j.
+// iteration j works on homes j-1-k (older) and j-k (newer).  Loads run PF
+// iterations ahead: the pair for iteration j+PF is loaded into home j+PF
+// meanwhile, so a load has PF iterations of stages to arrive (one iteration
+// of one wavefront does not cover the memory latency at the occupancy the LDS
+// ring allows), and NH = K+1+PF homes suffice; the march loop, unrolled by
+// NH, moves no data between registers.  Phases: the phase rows of pair j are
+// loaded in iteration j+1-PF and first used by stage 0 in iteration j+1;
+// register phases keep one home per psi home, the LDS ring keeps PF+1
+// register homes (pairs j+PF-1 .. j-1) and moves pair j-1's phase to the
+// ring at the end of iteration j.  complex64 runs PF = 2; complex128, the
+// time-dependent march and the fourth-order pass (whose m-table loads are
+// tied to the phase loads' distance) PF = 1.
 template <class T, bool TD>
 using PhaseT = std::conditional_t<TD, double2, typename T::PT>;
 template <class T, bool TD>
@@ -562,8 +567,14 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     constexpr int K = S + (LAST ? 1 : 0);
     constexpr int HL = (K + PPL - 1) / PPL;
     constexpr int NL = WaveRing<PT, S, PPL, LDS>::kSlots;
-    constexpr int NH = LDS ? ((K + 3) & ~1) : K + 2;  // even with the LDS ring
-    constexpr int NP = LDS ? 2 : NH;                   // phase homes
+    // load distance (iterations): complex128 rows already put twice the bytes
+    // in flight per load and its registers are full at two wavefronts per SIMD;
+    // the time-dependent march is bound by its arithmetic, not its loads
+    constexpr int PF = (U4 || TD || sizeof(R) == 8) ? 1 : 2;
+    constexpr int NH0 = K + 1 + PF;
+    constexpr int NP = LDS ? PF + 1 : NH0;             // phase homes
+    // with the LDS ring a multiple of NP, so every phase home index is static
+    constexpr int NH = LDS ? (NH0 + NP - 1) / NP * NP : NH0;
     static_assert(!U4 || (LDS && S == 5 && !CLOSED && !TD && PPL == 1),
                   "the fourth-order pass is 5 sub-steps, LDS ring, periodic, one pair per lane");
     const int nx = a.nx, ny = a.ny;
@@ -750,14 +761,18 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     // stored site depends on, and are skipped (a wavefront-uniform branch).
     int it = 0;
     load_psi(home[0]);
+    if constexpr (PF == 2) {
+        load_psi(home[1]);
+        load_phase(ph[0]);
+    }
     // One march iteration with static home indices (u = j mod NH).
     auto iteration = [&](auto U) {
         constexpr int u = decltype(U)::value;
-        // The last iteration loads one pair more than the march uses (always
+        // The last iterations load PF pairs more than the march uses (always
         // rows of the mesh): an unconditional load keeps the homes free of
         // merges.
-        load_psi(home[(u + 1) % NH]);
-        load_phase(ph[u % NP]);
+        load_psi(home[(u + PF) % NH]);
+        load_phase(ph[(u + PF - 1) % NP]);
         if constexpr (U4) load_phase_m(phm[(u + 1) % 2]);
         static_for<K>([&](auto KK) {
             constexpr int k = decltype(KK)::value;
