@@ -391,7 +391,7 @@ def profile_mode(p, psi0, V, args) -> int:
 
 
 def sweep_mode(p, psi0, V, args) -> int:
-    """Every candidate schedule (the tuner's, plus 7 and 8 steps per pass) for
+    """Every candidate schedule of the tuner (1-8 steps per pass) for
     exactly --profile-passes passes after a warm-up, each timed with HIP events
     on the current stream; one JSON line per dtype and schedule.  Run under
     rocprofv3 --pmc it also gives the HBM counters of every schedule."""
@@ -399,7 +399,7 @@ def sweep_mode(p, psi0, V, args) -> int:
     import paper_1208_2407_amd as tsq
     from paper_1208_2407_amd import autotune
 
-    cands = list(autotune.DEFAULT_CANDIDATES) + [(7, 0, 1, 2), (8, 0, 1, 2)]
+    cands = list(autotune.DEFAULT_CANDIDATES)
     stream = torch.cuda.current_stream()
     # reference copy of known size (1 GiB read + 1 GiB written) to scale the counters
     src = torch.empty(2**27, dtype=torch.float64, device="cuda")

@@ -379,6 +379,9 @@ class Plan:
         V = self._V if V is None else V
         if V is None:
             raise ValueError("no potential given")
+        torch = _torch()
+        if V.dtype != torch.float64 or not V.is_contiguous() or tuple(V.shape) != self.shape:
+            raise ValueError(f"V must be a contiguous float64 {self.shape} device tensor")
         ws = self.workspace()
         return tsq_observables(self.handle, psi.data_ptr(), V.data_ptr(), ws.data_ptr(),
                                ws.numel(), _stream_handle(psi.device))

@@ -19,11 +19,14 @@ Schedule = Tuple[int, int, int, int]
 
 # segment_rows 0 = one round of resident wavefronts; phase_store 1 = registers, 2 = LDS.
 # Not tried by default: 2 pairs per lane (twice the registers, one wavefront
-# per SIMD) and 7 or 8 steps per pass (a march loop larger than the
-# instruction cache); both stay available through tsq_plan_set_schedule.
+# per SIMD); it stays available through tsq_plan_set_schedule.  7 and 8 steps
+# per pass (LDS ring only) are tried: their march loop outgrows the instruction
+# cache, which costs complex64 more than it gains, but complex128's 7-step pass
+# measured 3% faster than its 6-step one at 4096^2.
 DEFAULT_CANDIDATES: List[Schedule] = (
     [(1, 0, 1, 1)]
     + [(S, 0, 1, store) for S in (2, 3, 4, 5, 6) for store in (1, 2)]
+    + [(7, 0, 1, 2), (8, 0, 1, 2)]
 )
 
 

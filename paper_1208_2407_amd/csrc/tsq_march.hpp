@@ -550,8 +550,9 @@ __device__ __forceinline__ PT zero_phase() {
 // register phases keep one home per psi home, the LDS ring keeps PF+1
 // register homes (pairs j+PF-1 .. j-1) and moves pair j-1's phase to the
 // ring at the end of iteration j.  complex64 runs PF = 2; complex128, the
-// time-dependent march and the fourth-order pass (whose m-table loads are
-// tied to the phase loads' distance) PF = 1.
+// time-dependent march and the fourth-order pass PF = 1.  The fourth-order
+// pass keeps PF+1 homes of m-table phases as well (its stage 2 takes the m
+// table).
 template <class T, bool TD>
 using PhaseT = std::conditional_t<TD, double2, typename T::PT>;
 template <class T, bool TD>
@@ -569,7 +570,8 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     constexpr int NL = WaveRing<PT, S, PPL, LDS>::kSlots;
     // load distance (iterations): complex128 rows already put twice the bytes
     // in flight per load and its registers are full at two wavefronts per SIMD;
-    // the time-dependent march is bound by its arithmetic, not its loads
+    // the time-dependent and fourth-order marches are bound by their
+    // arithmetic, not their loads (two ahead measured 2-8% slower there)
     constexpr int PF = (U4 || TD || sizeof(R) == 8) ? 1 : 2;
     constexpr int NH0 = K + 1 + PF;
     constexpr int NP = LDS ? PF + 1 : NH0;             // phase homes
@@ -631,16 +633,12 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
     const int fo = rev ? 1 : 0;  // row offset of F within a pair; G is at 1 - fo
     int rpsi = CLOSED ? 2 * tstart : wrap(2LL * tstart, ny);
     int rph = rpsi;
-    // fourth order: the m-table phase of the pair stage 2 completes in the
-    // next iteration, i.e. two pairs behind the pair whose phase `rph` loads
+    // fourth order: the m-table phase of the pair stage 2 completes PF
+    // iterations later, i.e. two pairs behind the pair whose phase `rph` loads
+    // in the same iteration (3 - PF pairs behind the first psi pair; the
+    // fourth-order pass is periodic only)
     int rphm = rpsi;
-    if constexpr (U4) {
-        rphm -= 2 * rstep_of(rev);
-        if constexpr (!CLOSED) {
-            rphm = rphm < 0 ? rphm + ny : rphm;
-            rphm = rphm >= ny ? rphm - ny : rphm;
-        }
-    }
+    if constexpr (U4) rphm = wrap((long long)rpsi - (3 - PF) * rstep_of(rev), ny);
     int qout = rev ? q1 - 1 + 2 * K : q0 - 2 * K;  // pair leaving the pipeline this iteration
 
     const int rstep = rev ? -2 : 2;
@@ -730,7 +728,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
 
     PairRows<R, SPL> home[NH];
     PhasePair<PT, SPL> ph[NP];
-    PhasePair<PT, SPL> phm[U4 ? 2 : 1];  // m-table phases (fourth order), two homes
+    PhasePair<PT, SPL> phm[U4 ? PF + 1 : 1];  // m-table phases (fourth order)
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
 #pragma unroll
@@ -745,7 +743,7 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         for (int i = 0; i < SPL; ++i) ph[h].f[i] = ph[h].g[i] = zero_phase<PT>();
     }
 #pragma unroll
-    for (int h = 0; h < (U4 ? 2 : 1); ++h) {
+    for (int h = 0; h < (U4 ? PF + 1 : 1); ++h) {
 #pragma unroll
         for (int i = 0; i < SPL; ++i) phm[h].f[i] = phm[h].g[i] = zero_phase<PT>();
     }
@@ -773,14 +771,14 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         // merges.
         load_psi(home[(u + PF) % NH]);
         load_phase(ph[(u + PF - 1) % NP]);
-        if constexpr (U4) load_phase_m(phm[(u + 1) % 2]);
+        if constexpr (U4) load_phase_m(phm[(u + PF) % (PF + 1)]);
         static_for<K>([&](auto KK) {
             constexpr int k = decltype(KK)::value;
             if (it > 2 * k)
             pipeline_stage<S, K, CLOSED, TD, U4, R, SPL, PT>(
                 k, home[(u - 1 - k + 2 * NH) % NH], home[(u - k + 2 * NH) % NH], a, xm,
                 rev ? q + k : q - k, rev, turns, [&](int kk) {
-                    if (U4 && kk == 2) return phm[U4 ? u % 2 : 0];
+                    if (U4 && kk == 2) return phm[U4 ? u % (PF + 1) : 0];
                     if (!LDS || kk == 0) return ph[(u - 1 - kk + 2 * NP) % NP];
                     int slot = wslot - kk;
                     if (slot < 0) slot += NL;

@@ -179,6 +179,131 @@ observables_partial(const void* __restrict__ psi, const double* __restrict__ V, 
     }
 }
 
+// Periodic meshes with an even number of columns: each lane owns two
+// neighbouring columns (16-byte loads of psi and V per row, as the march
+// issues), and the x-neighbours outside its pair come from the lanes beside
+// it by a DPP wavefront shift; only the first and last lanes of a wavefront
+// (and the last lane holding columns when the row ends inside the wavefront)
+// load theirs.  Work items are (chunk of 2 * kReduceThreads columns, band of
+// rows), walked as in observables_partial; fixed order, bitwise reproducible.
+__device__ __forceinline__ double lane_from_left(double v) {
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_from_right(double v) {
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// psi of sites l and l+1 (l even): complex128 two 16-byte loads, complex64 one.
+__device__ __forceinline__ void load_pair2(const void* psi, long long l, double (&re)[2],
+                                           double (&im)[2], C128) {
+    const double2* q = reinterpret_cast<const double2*>(psi) + l;
+    const double2 a = q[0], b = q[1];
+    re[0] = a.x; im[0] = a.y; re[1] = b.x; im[1] = b.y;
+}
+__device__ __forceinline__ void load_pair2(const void* psi, long long l, double (&re)[2],
+                                           double (&im)[2], C64) {
+    const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(psi) + l);
+    re[0] = a.x; im[0] = a.y; re[1] = a.z; im[1] = a.w;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kReduceThreads)
+observables_pairs(const void* __restrict__ psi, const double* __restrict__ V, int nx, int ny,
+                  double Jx, double Jy, double eps0, int band, double* __restrict__ partial) {
+    __shared__ double sn[kReduceThreads], se[kReduceThreads];
+    constexpr int U = 4;  // rows per step of the walk
+    constexpr int W = 2 * kReduceThreads;  // columns per chunk
+    double an = 0.0, ae = 0.0;
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int chunks = (nx + W - 1) / W;
+    const int bands = (ny + band - 1) / band;
+    const long long items = (long long)chunks * bands;
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+        const int x0 = (int)(it % chunks) * W + 2 * (int)threadIdx.x;
+        const int y0 = (int)(it / chunks) * band;
+        const int y1 = min(y0 + band, ny);
+        // every lane takes part in the shifts; lanes past the row load nothing
+        const bool live = x0 < nx;
+        const bool edge_l = lane == 0;
+        const bool edge_r = lane == kWaveSize - 1 || x0 + 2 >= nx;
+        const int xl = x0 == 0 ? nx - 1 : x0 - 1;
+        const int xr = x0 + 2 >= nx ? 0 : x0 + 2;
+        const int xc = live ? x0 : 0;
+        auto load_pairs = [&](int y, double (&re)[2], double (&im)[2]) {
+            re[0] = re[1] = im[0] = im[1] = 0.0;
+            if (live) load_pair2(psi, (long long)y * nx + xc, re, im, T());
+        };
+        double ur[2], ui[2], cr[2], ci[2];
+        load_pairs(y0 == 0 ? ny - 1 : y0 - 1, ur, ui);
+        load_pairs(y0, cr, ci);
+        // one row: the row below is loaded by the caller, V and the edge
+        // neighbours of row y here
+        auto row = [&](int y, const double (&dr)[2], const double (&di)[2], double2 v) {
+            double lr = lane_from_left(cr[1]), li = lane_from_left(ci[1]);
+            double rr = lane_from_right(cr[0]), ri = lane_from_right(ci[0]);
+            if (live && edge_l) load_site(psi, (long long)y * nx + xl, lr, li, T());
+            if (live && edge_r) load_site(psi, (long long)y * nx + xr, rr, ri, T());
+            if (live) {
+                site_energy<T>(cr[0], ci[0], ur[0], ui[0], dr[0], di[0], cr[1], ci[1], lr, li, v.x,
+                               Jx, Jy, eps0, an, ae);
+                site_energy<T>(cr[1], ci[1], ur[1], ui[1], dr[1], di[1], rr, ri, cr[0], ci[0], v.y,
+                               Jx, Jy, eps0, an, ae);
+            }
+        };
+        auto load_v = [&](int y) {
+            return live ? *reinterpret_cast<const double2*>(V + (long long)y * nx + xc)
+                        : make_double2(0.0, 0.0);
+        };
+        int y = y0;
+        for (; y + U <= y1; y += U) {
+            double dr[U][2], di[U][2];
+            double2 v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                load_pairs(y + k + 1 == ny ? 0 : y + k + 1, dr[k], di[k]);
+                v[k] = load_v(y + k);
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                row(y + k, dr[k], di[k], v[k]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    ur[i] = cr[i]; ui[i] = ci[i];
+                    cr[i] = dr[k][i]; ci[i] = di[k][i];
+                }
+            }
+        }
+        for (; y < y1; ++y) {
+            double dr[2], di[2];
+            load_pairs(y + 1 == ny ? 0 : y + 1, dr, di);
+            row(y, dr, di, load_v(y));
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ur[i] = cr[i]; ui[i] = ci[i];
+                cr[i] = dr[i]; ci[i] = di[i];
+            }
+        }
+    }
+    sn[threadIdx.x] = an;
+    se[threadIdx.x] = ae;
+    __syncthreads();
+    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sn[threadIdx.x] += sn[threadIdx.x + w];
+            se[threadIdx.x] += se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sn[0];
+        partial[2 * blockIdx.x + 1] = se[0];
+    }
+}
+
 __global__ void __launch_bounds__(kReduceThreads)
 observables_final(const double* __restrict__ partial, int nblocks, double* __restrict__ result) {
     __shared__ double sn[kReduceThreads], se[kReduceThreads];
@@ -245,15 +370,27 @@ hipError_t launch_observables(int dtype, const void* psi, const double* V, int n
                               double Jx, double Jy, double eps0, bool closed, double* partial,
                               int nblocks, double* result, hipStream_t s) {
     const int cl = closed ? 1 : 0;
+    // periodic meshes (even sides) with 16-byte aligned psi and V take the
+    // two-column kernel
+    const bool aligned = reinterpret_cast<uintptr_t>(psi) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(V) % 16 == 0;
+    const bool pairs = !closed && (nx % 2) == 0 && aligned;
+    const int width = pairs ? 2 * kReduceThreads : kReduceThreads;
     // bands of rows sized so the work items fill `nblocks` blocks once
-    const long long chunks = (nx + kReduceThreads - 1) / kReduceThreads;
+    const long long chunks = (nx + width - 1) / width;
     long long bands = nblocks / chunks;
     if (bands < 1) bands = 1;
     if (bands > ny) bands = ny;
     const int band = (int)((ny + bands - 1) / bands);
     const long long items = chunks * ((ny + band - 1) / band);
     if (items < nblocks) nblocks = (int)items;
-    if (dtype == 1)
+    if (pairs && dtype == 1)
+        hipLaunchKernelGGL(observables_pairs<C128>, dim3(nblocks), dim3(kReduceThreads), 0, s,
+                           psi, V, nx, ny, Jx, Jy, eps0, band, partial);
+    else if (pairs)
+        hipLaunchKernelGGL(observables_pairs<C64>, dim3(nblocks), dim3(kReduceThreads), 0, s,
+                           psi, V, nx, ny, Jx, Jy, eps0, band, partial);
+    else if (dtype == 1)
         hipLaunchKernelGGL(observables_partial<C128>, dim3(nblocks), dim3(kReduceThreads), 0, s,
                            psi, V, nx, ny, Jx, Jy, eps0, cl, band, partial);
     else

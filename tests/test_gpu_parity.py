@@ -119,7 +119,7 @@ def test_bloch_closed_form_4096():
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("shape", [(2, 2), (6, 4), (300, 258), (1024, 1026)])
+@pytest.mark.parametrize("shape", [(2, 2), (6, 4), (130, 6), (300, 258), (1024, 1026)])
 def test_observables_match_oracle(shape, dtype):
     nx, ny = shape
     psi0 = as_input(wl.random_state(nx, ny, 31) * 1.3, dtype)
@@ -133,6 +133,28 @@ def test_observables_match_oracle(shape, dtype):
     assert abs(e - e0) <= 1e-12 * max(1.0, abs(e0))
     # fixed reduction order: bitwise reproducible
     assert plan.observables(psi, Vd) == (n, e)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_observables_any_alignment(dtype):
+    """psi or V off a 16-byte boundary (views one element into a buffer) take the
+    one-column kernel; both kernels agree with the oracle to the same bounds."""
+    nx, ny = 258, 130
+    psi0 = as_input(wl.random_state(nx, ny, 33), dtype)
+    V = wl.random_potential(nx, ny, 34)
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    n0, e0 = oracle.observables(psi0, V, **ANISO)
+    plan = tsq.Plan(nx, ny, 0.1, dtype, device="cuda", **ANISO)
+    pbuf = torch.zeros(nx * ny + 1, dtype=tdt, device="cuda")
+    vbuf = torch.zeros(nx * ny + 1, dtype=torch.float64, device="cuda")
+    for po, vo in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        psi = pbuf[po:po + nx * ny].view(ny, nx)
+        Vd = vbuf[vo:vo + nx * ny].view(ny, nx)
+        psi.copy_(torch.from_numpy(psi0).to(tdt))
+        Vd.copy_(torch.from_numpy(V))
+        n, e = plan.observables(psi, Vd)
+        assert abs(n - n0) <= 1e-13 * abs(n0), (po, vo)
+        assert abs(e - e0) <= 1e-12 * max(1.0, abs(e0)), (po, vo)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])

@@ -168,6 +168,34 @@ def test_td_large_phases(dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_phase_factor_alone(dtype):
+    """With a mass so large that every kinetic rotation rounds to the identity, a
+    step is its phase factor alone: psi_n = psi_0 exp(-i sum_k (theta0 + f_k w)).
+    Checked site by site against that closed form over angles of up to ~1e3 rad
+    of either sign (the angle-addition reduction, the 256-factor table with
+    negative indices, the short series) and against the oracle."""
+    nx, ny = 130, 34
+    rng = np.random.default_rng(51)
+    psi0 = as_input(wl.random_state(nx, ny, 52), dtype)
+    V0 = rng.uniform(-2000.0, 2000.0, (ny, nx))
+    W = rng.uniform(-300.0, 300.0, (ny, nx))
+    f = rng.uniform(-2.0, 2.0, 7)
+    dt, mass = 0.5, 1e30
+    eps0 = 2.0 / mass
+    theta0 = dt * (V0 + eps0)
+    w = dt * W
+    want = psi0 * np.exp(-1j * (len(f) * theta0 + f.sum() * w))
+    oracle_run = oracle.evolve_td(psi0, V0, W, f, dt, mass=mass)
+    tol = 1e-11 if dtype == "c128" else 1e-6  # complex64: 7 roundings of 2^-24
+    assert np.max(np.abs(oracle_run - want)) <= 1e-11
+    for S in (1, 3, 5):
+        got = gpu_evolve_td(psi0, V0, W, f, dt, dtype, steps_per_pass=S, mass=mass)
+        err = np.max(np.abs(got - want) / np.abs(want))
+        log(f"  td phase alone {dtype} S={S}: max site rel error {err:.3e}")
+        assert err <= tol, (S, err)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_td_forward_then_backward(dtype):
     p = wl.packets_and_bumps(512, 384, 21, 0.05, 150, dtype)
     psi0 = as_input(wl.initial_state(p).numpy(), dtype)
