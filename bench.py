@@ -565,6 +565,15 @@ def run_served(args) -> dict:
         "block_steps": srv.block, "hbm_budget_bytes": srv.budget,
         "schedules": srv.schedule_report(), "server": st,
     }
+    # utilization rho = offered load / the server's capacity, the capacity being its
+    # rate when saturated: the first 5 s of the trace, every request available at once
+    sat_trace = [r for r in trace if r.arrival < 5.0]
+    sat = serve.Server(block_steps=srv.block, schedules=srv.schedules).run(
+        sat_trace, realtime=False).summary()
+    out["capacity_site_steps_per_s"] = sat["site_steps_per_s"]
+    out["utilization_rho"] = offered / sat["site_steps_per_s"] if sat["site_steps_per_s"] else None
+    log(f"served: saturated capacity {sat['site_steps_per_s']:.3e} site-steps/s, "
+        f"rho {out['utilization_rho']:.2f}")
     if args.fifo_seconds > 0:
         fifo_trace = [r for r in trace if r.arrival < args.fifo_seconds]
         batched_prefix = serve.Server(block_steps=srv.block,
