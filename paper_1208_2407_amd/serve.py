@@ -183,9 +183,13 @@ class Server:
                 # stream (default priority) so the two batched calls overlap
                 batches = []
                 cur = torch.cuda.current_stream(self.device)
-                side.wait_stream(cur)
-                for dtype, stream in (("c64", cur), ("c128", side)):
-                    group = [s for s in resident if s.req.problem.dtype == dtype]
+                groups = {dt: [s for s in resident if s.req.problem.dtype == dt]
+                          for dt in ("c64", "c128")}
+                two = bool(groups["c64"]) and bool(groups["c128"])
+                if two:
+                    side.wait_stream(cur)
+                for dtype, stream in (("c64", cur), ("c128", side if two else cur)):
+                    group = groups[dtype]
                     if not group:
                         continue
                     steps = [min(self.block, s.remaining) for s in group]
@@ -207,7 +211,8 @@ class Server:
                     batches.append(b)
                     for s, n in zip(group, steps):
                         s.remaining -= n
-                cur.wait_stream(side)
+                if two:
+                    cur.wait_stream(side)
                 ev = torch.cuda.Event()
                 ev.record(cur)
                 finishing = [s for s in resident if s.remaining == 0]

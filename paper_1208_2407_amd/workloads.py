@@ -165,6 +165,15 @@ def batch_problems(count: int = 512, seed: int = 4, steps: int = 500, lo: int = 
 
 # ---------------------------------------------------------------- fields
 
+def _dev(a: np.ndarray, device) -> torch.Tensor:
+    """A host array on `device`: to a GPU through pinned memory, asynchronously on the
+    current stream (the request loop of the server generates inputs between launches)."""
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if torch.device(device).type != "cuda":
+        return t.to(device)
+    return t.pin_memory().to(device, non_blocking=True)
+
+
 def _coords(n: int, d: float, lo: int, hi: int) -> np.ndarray:
     return (np.arange(lo, hi, dtype=np.float64) - n / 2) * d
 
@@ -197,15 +206,15 @@ def initial_state(p: Problem, device="cpu", dtype=torch.complex128,
     inv = 1.0 / math.sqrt(state_norm2(p))
     xs = _coords(p.nx, p.dx, c0, c1)
     ys = _coords(p.ny, p.dy, r0, r1)
-    F = torch.from_numpy(np.stack([_packet_1d(xs, q.x0, q.kx, q.sigma) for q in p.packets]))
+    F = np.stack([_packet_1d(xs, q.x0, q.kx, q.sigma) for q in p.packets])
     a = np.array([np.exp(1j * q.theta) * inv for q in p.packets])
     G = np.stack([_packet_1d(ys, q.y0, q.ky, q.sigma) for q in p.packets]) * a[:, None]
-    G = torch.from_numpy(np.ascontiguousarray(G.T))          # (rows, K)
-    F = F.to(device)
+    F = _dev(F, device)
+    G = _dev(G.T, device)                                    # (rows, K)
     out = torch.empty((r1 - r0, c1 - c0), dtype=dtype, device=device)
     for s in range(0, r1 - r0, chunk_rows):
         e = min(r1 - r0, s + chunk_rows)
-        out[s:e] = (G[s:e].to(device) @ F).to(dtype)
+        out[s:e] = (G[s:e] @ F).to(dtype)
     return out
 
 
@@ -217,21 +226,21 @@ def potential(p: Problem, device="cpu", rows: Optional[Tuple[int, int]] = None,
     xs = _coords(p.nx, p.dx, c0, c1)
     ys = _coords(p.ny, p.dy, r0, r1)
     k = 0.5 * p.mass * p.omega * p.omega
-    vx = torch.from_numpy(k * xs * xs + p.v0).to(device)
-    vy = torch.from_numpy(k * ys * ys).to(device)
+    vx = _dev(k * xs * xs + p.v0, device)
+    vy = _dev(k * ys * ys, device)
     nb = len(p.bumps)
     out = torch.empty((r1 - r0, c1 - c0), dtype=torch.float64, device=device)
     if nb:
         U = np.stack([np.exp(-((xs - b.cx) ** 2) / (2 * b.width ** 2)) for b in p.bumps])
         W = np.stack([b.amp * np.exp(-((ys - b.cy) ** 2) / (2 * b.width ** 2))
                       for b in p.bumps])
-        U = torch.from_numpy(U).to(device)
-        W = torch.from_numpy(np.ascontiguousarray(W.T))
+        U = _dev(U, device)
+        W = _dev(W.T, device)
     for s in range(0, r1 - r0, chunk_rows):
         e = min(r1 - r0, s + chunk_rows)
         blk = vy[s:e, None] + vx[None, :]
         if nb:
-            blk = blk + W[s:e].to(device) @ U
+            blk = blk + W[s:e] @ U
         out[s:e] = blk
     return out
 
