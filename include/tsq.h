@@ -207,9 +207,12 @@ int tsq_set_potential_td(tsq_plan* plan, const double* V0_dev, const double* W_d
  * `steps` finite doubles, read before the call returns) as the modulation at
  * its midpoint.  Consecutive calls continue the evolution: pass each call the
  * modulations of its own steps.  Results are bitwise identical across
- * schedules.  Errors: TSQ_ERR_ARG (null, steps < 0, a non-finite f, 2 pairs
- * per lane, misaligned psi), TSQ_ERR_STATE (tsq_set_potential_td not called
- * with this workspace), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
+ * schedules.  Each step's phase angle dt (V0 + f_n W + eps0) / hbar must stay
+ * below 2^45 in magnitude at every site (the in-kernel reduction's range; not
+ * checked: larger angles give wrong phases).  Errors: TSQ_ERR_ARG (null,
+ * steps < 0, a non-finite f, 2 pairs per lane, misaligned psi), TSQ_ERR_STATE
+ * (tsq_set_potential_td not called with this workspace), TSQ_ERR_WORKSPACE,
+ * TSQ_ERR_DEVICE. */
 int tsq_evolve_td(tsq_plan* plan, void* psi_dev, int64_t steps, const double* f_host, void* ws,
                   size_t ws_bytes, void* stream);
 
@@ -267,7 +270,8 @@ int tsq_batch_upload(tsq_batch* batch, void* bws, size_t bws_bytes, void* stream
 /* Enqueue every pass of every problem on `stream` (kernels and, for a
  * problem whose pass count is odd and cannot be split, one device copy).
  * With use_graph != 0 the sequence is captured into a HIP graph on the first
- * call (stream must not be the null stream) and replayed by later calls.
+ * call (stream must not be the null stream) and replayed by later calls, on
+ * any stream.
  * Each call advances every problem by its step count again.
  * Errors: TSQ_ERR_STATE (not uploaded), TSQ_ERR_ARG, TSQ_ERR_DEVICE. */
 int tsq_batch_launch(tsq_batch* batch, int32_t use_graph, void* stream);

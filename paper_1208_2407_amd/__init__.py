@@ -392,8 +392,9 @@ class Batch:
 
     ``plans[i]`` (with its potential set) evolves ``psis[i]`` by ``steps[i]``;
     all plans share one dtype.  :meth:`launch` enqueues every pass of every
-    problem on the current stream, optionally through a captured HIP graph
-    (replayed on later calls, on a side stream ordered with the current one).
+    problem on the current stream, optionally through a HIP graph (captured on
+    the first such call on a side stream ordered with the current one, replayed
+    by later calls on the current stream).
     """
 
     def __init__(self, plans, psis, steps, schedule=(0, 0, 0, 0)):
@@ -414,6 +415,7 @@ class Batch:
         tsq_batch_upload(self.handle, self.bws.data_ptr(), self.bws.numel(),
                          _stream_handle(self.device))
         self._side = None
+        self._captured = False
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -433,12 +435,18 @@ class Batch:
         if not use_graph:
             tsq_batch_launch(self.handle, False, _stream_handle(self.device))
             return
+        if self._captured:  # replay on the current stream
+            tsq_batch_launch(self.handle, True, _stream_handle(self.device))
+            return
+        # capture on a side stream (the current one may be the null stream, which
+        # cannot capture), ordered with the current one
         if self._side is None:
             self._side = torch.cuda.Stream(device=self.device)
         cur = torch.cuda.current_stream(self.device)
         self._side.wait_stream(cur)
         tsq_batch_launch(self.handle, True, self._side.cuda_stream)
         cur.wait_stream(self._side)
+        self._captured = True
 
 
 def _dtype_name(t) -> str:

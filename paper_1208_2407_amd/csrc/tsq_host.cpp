@@ -528,8 +528,8 @@ int tsq_batch_launch(tsq_batch* b, int32_t use_graph, void* stream) {
         int rc = enqueue_batch(b, s);
         return rc ? rc : ok();
     }
-    if (s == nullptr) return fail(TSQ_ERR_ARG, "graph capture needs a non-null stream");
     if (!b->exec) {
+        if (s == nullptr) return fail(TSQ_ERR_ARG, "graph capture needs a non-null stream");
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return fail(TSQ_ERR_DEVICE, "begin capture: %s", hipGetErrorString(e));
         int rc = enqueue_batch(b, s);
