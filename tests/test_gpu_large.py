@@ -35,8 +35,13 @@ def test_mesh32768_complex64_crops():
                       psi[y0:y0 + W, x0:x0 + W].cpu().numpy().astype(np.complex128),
                       V[y0:y0 + W, x0:x0 + W].cpu().numpy()))
     plan = tsq.Plan(n, n, p.dt, "c64")
-    plan.set_schedule(6, 0, 1, 1)   # the schedule the tuner picks for this mesh in bench.py
     plan.set_potential(V)
+    psi0 = psi.clone()
+    # the schedules the tuner picks between for this mesh in bench.py: 6 steps per
+    # pass, 512-row segments, register or LDS phase ring (bitwise equal)
+    plan.set_schedule(6, 512, 1, 2)
+    plan.evolve(psi0, p.steps)
+    plan.set_schedule(6, 512, 1, 1)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -46,6 +51,8 @@ def test_mesh32768_complex64_crops():
     ms = e0.elapsed_time(e1)
     log(f"  {n}^2 c64 x {p.steps} steps: {ms:.1f} ms, {n * n * p.steps / (ms * 1e-3):.3e} site-steps/s, "
         f"schedule {plan.schedule()}, norm {norm:.9f}")
+    assert torch.equal(psi, psi0)
+    del psi0
     assert abs(norm - 1.0) < 1e-5
     errs = []
     for (y0, x0, cin, cV) in crops:

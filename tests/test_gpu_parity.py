@@ -160,17 +160,18 @@ def test_observables_any_alignment(dtype):
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_mesh4096_sampled_windows(dtype):
     """Full 4096^2 mesh of the packets-and-bumps recipe in the benchmark's launch
-    configurations (5 and 6 steps per pass with the register phase ring, one round of
-    wavefronts: the schedules the tuner picks there), 50 steps; sampled 256^2 windows
-    checked against oracle runs on the window plus its light cone (2N+1 sites per side,
-    rounded up to an even margin)."""
+    configurations (5 and 6 steps per pass with the register phase ring, 8 with the LDS
+    ring, one round of wavefronts: the schedules the tuner picks there), 50 steps;
+    sampled 256^2 windows checked against oracle runs on the window plus its light cone
+    (2N+1 sites per side, rounded up to an even margin)."""
     p = wl.packets_and_bumps(4096, 4096, 2, 0.05, 50, dtype)
     # the packets plus seeded noise over the whole mesh: every window holds a state
     psi0 = wl.initial_state(p).numpy() + 0.5 * wl.random_state(4096, 4096, 62)
     V = wl.potential(p).numpy()
-    runs = [gpu_evolve(psi0, V, p.dt, p.steps, dtype, steps_per_pass=S, phase_store=1)
-            for S in (5, 6)]
-    assert np.array_equal(runs[0], runs[1])
+    runs = [gpu_evolve(psi0, V, p.dt, p.steps, dtype, steps_per_pass=S, phase_store=st)
+            for S, st in ((5, 1), (6, 1), (8, 2))]
+    for r in runs[1:]:
+        assert np.array_equal(runs[0], r)
     h = w = 256
     # windows centred on the packets and one across the periodic corner
     wins = [((int(q.y0 + 2048) - h // 2) // 2 * 2, (int(q.x0 + 2048) - w // 2) // 2 * 2)
