@@ -113,52 +113,58 @@ __device__ __forceinline__ void apply_phase(float& re, float& im, const float4 p
 
 // Phase factor of step n under V0 + f_n W, g * exp(-i x) with x = theta0 + f_n w
 // (tw = (theta0, w) of the site, f = f_n), in FP64, by angle addition:
-// x = j pi/128 + r with j the integer nearest x * 128/pi and |r| <= pi/256,
-// exp(-i x) = exp(-i j pi/128) exp(-i r).  `turns` holds the 256 factors
-// g exp(-i j pi/128), j mod 256 (g is the cosine restoration of a periodic
-// mesh's tangent form, 1 between walls); exp(-i r) comes from the Taylor
-// series of cos and sin on the small interval.  The factor is a function of
-// (theta0, w, f_n) alone, so every schedule forms the same bits.
-// Reduction (Cody and Waite): pi/128 split into C1 (the double nearest) and
-// C2 (the double nearest pi/128 - C1), the product j C1 exact inside an FMA;
-// j comes from adding 1.5 * 2^52 inside the FMA that forms x * 128/pi, after
+// x = j pi/512 + r with j the integer nearest x * 512/pi and |r| <= pi/1024,
+// exp(-i x) = exp(-i j pi/512) exp(-i r).  `turns` holds the kTurns = 1024
+// factors g exp(-i j pi/512), j mod 1024 (g is the cosine restoration of a
+// periodic mesh's tangent form, 1 between walls); exp(-i r) comes from the
+// Taylor series of cos and sin on the small interval.  The factor is a
+// function of (theta0, w, f_n) alone, so every schedule forms the same bits.
+// Reduction (Cody and Waite): pi/512 split into C1 (the double nearest) and
+// C2 (the double nearest pi/512 - C1), the product j C1 exact inside an FMA;
+// j comes from adding 1.5 * 2^52 inside the FMA that forms x * 512/pi, after
 // which the low bits of the sum's significand hold j (|x| < 2^45).
-// FULL (complex128): sin r through r^5, cos r through r^6 (first omitted terms
-// below 1e-17 and 1e-19).  Otherwise (complex64, whose state keeps 24 bits):
-// sin r through r^3, cos r through r^4 (below 2.4e-12 and 5e-15).
-template <bool FULL>
-__device__ __forceinline__ double2 td_factor(const double2 tw, double f, const double2* turns) {
-    const double C1 = 0x1.921fb54442d18p-6;   // pi/128 rounded to double
-    const double C2 = 0x1.1a62633145c07p-60;  // pi/128 - C1 rounded to double
+// FULL (complex128): sin r through r^5, cos r through r^4 (first omitted terms
+// below 1e-21 and 2e-18).  Otherwise (complex64, whose state keeps 24 bits):
+// sin r through r^3, cos r through r^2 (below 3e-15 and 4e-12).
+struct TdTurn {
+    double r;   // reduced angle, |r| <= pi/1024
+    double2 u;  // g exp(-i j pi/512) from the table
+};
+__device__ __forceinline__ TdTurn td_reduce(const double2 tw, double f, const double2* turns) {
+    const double C1 = 0x1.921fb54442d18p-8;   // pi/512 rounded to double
+    const double C2 = 0x1.1a62633145c07p-62;  // pi/512 - C1 rounded to double
     const double shifter = 0x1.8p52;          // 1.5 * 2^52: unit in the last place 1
     const double x = mad(f, tw.y, tw.x);
-    const double t = mad(x, 0x1.45f306dc9c883p+5, shifter);  // x * (128/pi) + shifter
+    const double t = mad(x, 0x1.45f306dc9c883p+7, shifter);  // x * (512/pi) + shifter
     const double j = t - shifter;                              // exact
-    const unsigned idx = (unsigned)__double2loint(t) & 255u;   // j mod 256
+    const unsigned idx = (unsigned)__double2loint(t) & (unsigned)(kTurns - 1);  // j mod 1024
     double r = mad(-j, C1, x);
     r = mad(-j, C2, r);
+    return TdTurn{r, turns[idx]};
+}
+template <bool FULL>
+__device__ __forceinline__ double2 td_combine(const TdTurn& q) {
+    const double r = q.r;
     const double r2 = r * r;
-    double ps = -1.0 / 6.0, pc = 1.0 / 24.0;
+    double ps = -1.0 / 6.0, pc = -0.5;
     if constexpr (FULL) {
         ps = mad(r2, 1.0 / 120.0, ps);
-        pc = mad(r2, -1.0 / 720.0, pc);
+        pc = mad(r2, 1.0 / 24.0, pc);
     }
-    const double sr = mad(r * r2, ps, r);          // sin r
-    const double cr = mad(r2, mad(r2, pc, -0.5), 1.0);  // cos r
-    const double2 u = turns[idx];                  // g exp(-i j pi/128)
+    const double sr = mad(r * r2, ps, r);   // sin r
+    const double cr = mad(r2, pc, 1.0);     // cos r
+    const double2 u = q.u;
     // (u.x + i u.y)(cr - i sr)
     return make_double2(mad(u.x, cr, u.y * sr), mad(u.y, cr, -(u.x * sr)));
 }
 
 // Apply the factor: complex128 in place; complex64 widened to FP64,
 // multiplied, rounded once.
-__device__ __forceinline__ void apply_phase_td(double& re, double& im, const double2 tw, double f,
-                                               const double2* turns) {
-    apply_phase(re, im, td_factor<true>(tw, f, turns));
+__device__ __forceinline__ void apply_phase_td(double& re, double& im, const TdTurn& q) {
+    apply_phase(re, im, td_combine<true>(q));
 }
-__device__ __forceinline__ void apply_phase_td(float& re, float& im, const double2 tw, double f,
-                                               const double2* turns) {
-    const double2 p = td_factor<false>(tw, f, turns);
+__device__ __forceinline__ void apply_phase_td(float& re, float& im, const TdTurn& q) {
+    const double2 p = td_combine<false>(q);
     const double r = re, i = im;
     re = (float)mad(r, p.x, -(i * p.y));
     im = (float)mad(r, p.y, i * p.x);
@@ -334,11 +340,22 @@ __device__ __forceinline__ void phase_row(Row<R, SPL>& w, const PT* p) {
     for (int i = 0; i < SPL; ++i) apply_phase(w.re[i], w.im[i], p[i]);
 }
 
+// Both rows of a pair: every site's reduction and table read first, so the
+// LDS reads are in flight together, then the factors.
 template <class R, int SPL>
-__device__ __forceinline__ void phase_row_td(Row<R, SPL>& w, const double2* p, double f,
-                                             const double2* turns) {
+__device__ __forceinline__ void phase_rows_td(Row<R, SPL>& a, Row<R, SPL>& b, const double2* pa,
+                                              const double2* pb, double f, const double2* turns) {
+    TdTurn qa[SPL], qb[SPL];
 #pragma unroll
-    for (int i = 0; i < SPL; ++i) apply_phase_td(w.re[i], w.im[i], p[i], f, turns);
+    for (int i = 0; i < SPL; ++i) {
+        qa[i] = td_reduce(pa[i], f, turns);
+        qb[i] = td_reduce(pb[i], f, turns);
+    }
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+        apply_phase_td(a.re[i], a.im[i], qa[i]);
+        apply_phase_td(b.re[i], b.im[i], qb[i]);
+    }
 }
 
 // Calls f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
@@ -452,8 +469,7 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
             even_x_t(o.g, a.ehxs);
             pair_y_t(o.f, o.g, a.ehys);
             if constexpr (TD) {
-                phase_row_td(o.f, ph.f, a.g[k], turns);
-                phase_row_td(o.g, ph.g, a.g[k], turns);
+                phase_rows_td(o.f, o.g, ph.f, ph.g, a.g[k], turns);
             } else {
                 phase_row(o.f, ph.f);
                 phase_row(o.g, ph.g);
@@ -479,8 +495,7 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
         const R eys = ey_ok ? a.ehys : R(0), eyd = ey_ok ? a.ehyd : R(0);
         pair_y(o.f, o.g, eys, eyd);
         if constexpr (TD) {
-            phase_row_td(o.f, ph.f, a.g[k], turns);
-            phase_row_td(o.g, ph.g, a.g[k], turns);
+            phase_rows_td(o.f, o.g, ph.f, ph.g, a.g[k], turns);
         } else {
             phase_row(o.f, ph.f);
             phase_row(o.g, ph.g);
@@ -838,9 +853,13 @@ march_kernel(const MarchArgs<typename T::R> a) {
     const int ngroups = (a.nstrips + kWavesPerBlock - 1) / kWavesPerBlock;
     if (lb >= ngroups * a.nsegs) return;  // uniform per block
     if constexpr (TD) {
-        // the time-dependent phase's table of 256 factors, one per thread
-        static_assert(kTurns == kWaveSize * kWavesPerBlock, "one table entry per thread");
-        turns[threadIdx.x] = reinterpret_cast<const double2*>(a.ptab2)[threadIdx.x];
+        // the time-dependent phase's table of kTurns factors, kTurns / 256 per thread
+        constexpr int kThreads = kWaveSize * kWavesPerBlock;
+        static_assert(kTurns % kThreads == 0, "whole table entries per thread");
+#pragma unroll
+        for (int e = 0; e < kTurns / kThreads; ++e)
+            turns[threadIdx.x + e * kThreads] =
+                reinterpret_cast<const double2*>(a.ptab2)[threadIdx.x + e * kThreads];
         __syncthreads();
     }
     const int seg = lb / ngroups;

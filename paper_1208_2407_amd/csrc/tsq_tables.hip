@@ -64,13 +64,13 @@ __global__ void td_table(const double* __restrict__ V0, const double* __restrict
         T[l] = make_double2(dt * (V0[l] + eps0) / hbar, dt * W[l] / hbar);
 }
 
-// The march's factors scale * exp(-i j pi/128), j = 0 .. kTurns-1 (j / 128 is
+// The march's factors scale * exp(-i j pi/512), j = 0 .. kTurns-1 (j / 512 is
 // exact, so sincospi sees the angle without rounding).
 __global__ void td_turns(double2* __restrict__ U, double scale) {
-    const int j = threadIdx.x;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= kTurns) return;
     double sn, cs;
-    sincospi((double)j / 128.0, &sn, &cs);
+    sincospi((double)j / 512.0, &sn, &cs);
     U[j] = make_double2(scale * cs, -(scale * sn));
 }
 
@@ -354,8 +354,8 @@ hipError_t launch_td_table(const double* V0, const double* W, void* table, void*
                        reinterpret_cast<double2*>(table), sites, dt, eps0, hbar);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(td_turns, dim3(1), dim3(kTurns), 0, s, reinterpret_cast<double2*>(turns),
-                       scale);
+    hipLaunchKernelGGL(td_turns, dim3((kTurns + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<double2*>(turns), scale);
     return hipGetLastError();
 }
 
