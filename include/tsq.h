@@ -208,7 +208,7 @@ int tsq_set_potential_td(tsq_plan* plan, const double* V0_dev, const double* W_d
  * its midpoint.  Consecutive calls continue the evolution: pass each call the
  * modulations of its own steps.  Results are bitwise identical across
  * schedules.  Each step's phase angle dt (V0 + f_n W + eps0) / hbar must stay
- * below 2^45 in magnitude at every site (the in-kernel reduction's range; not
+ * below 2^42 in magnitude at every site (the in-kernel reduction's range; not
  * checked: larger angles give wrong phases).  Errors: TSQ_ERR_ARG (null,
  * steps < 0, a non-finite f, 2 pairs per lane, misaligned psi), TSQ_ERR_STATE
  * (tsq_set_potential_td not called with this workspace), TSQ_ERR_WORKSPACE,

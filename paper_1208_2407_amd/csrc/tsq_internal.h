@@ -48,7 +48,7 @@ constexpr int kMaxSteps = 8;     // deepest fusion (phase ring in LDS)
 constexpr int kMaxRegSteps = 6;  // deepest fusion with the phase ring in registers
 constexpr int kMaxRegSteps2 = 4; // ... with two x-pairs per lane
 constexpr int kMaxTdSteps = 6;   // deepest fusion with a time-dependent potential
-constexpr int kTurns = 1024;     // time-dependent phase: factors exp(-i j pi/512), j mod 1024
+constexpr int kTurns = 2048;     // time-dependent phase: factors exp(-i j pi/1024), j mod 2048
 constexpr int kWaveSize = 64;
 constexpr int kWavesPerBlock = 4;
 
@@ -238,7 +238,7 @@ hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long 
 // Table of the time-dependent potential V0 + f(t) W: per site the phase angle
 // theta0 = dt (V0 + eps0) / hbar and its modulation w = dt W / hbar, as a
 // double2 (16 B/site, both dtypes); step n's phase is exp(-i (theta0 + f_n w)).
-// `turns` receives the kTurns factors scale * exp(-i j pi/512) (double2) the
+// `turns` receives the kTurns factors scale * exp(-i j pi/1024) (double2) the
 // march composes each step's factor from.
 hipError_t launch_td_table(const double* V0, const double* W, void* table, void* turns,
                            long long sites, double dt, double eps0, double hbar, double scale,

@@ -113,46 +113,49 @@ __device__ __forceinline__ void apply_phase(float& re, float& im, const float4 p
 
 // Phase factor of step n under V0 + f_n W, g * exp(-i x) with x = theta0 + f_n w
 // (tw = (theta0, w) of the site, f = f_n), in FP64, by angle addition:
-// x = j pi/512 + r with j the integer nearest x * 512/pi and |r| <= pi/1024,
-// exp(-i x) = exp(-i j pi/512) exp(-i r).  `turns` holds the kTurns = 1024
-// factors g exp(-i j pi/512), j mod 1024 (g is the cosine restoration of a
+// x = j pi/1024 + r with j the integer nearest x * 1024/pi and |r| <= pi/2048,
+// exp(-i x) = exp(-i j pi/1024) exp(-i r).  `turns` holds the kTurns = 2048
+// factors g exp(-i j pi/1024), j mod 2048 (g is the cosine restoration of a
 // periodic mesh's tangent form, 1 between walls); exp(-i r) comes from the
 // Taylor series of cos and sin on the small interval.  The factor is a
 // function of (theta0, w, f_n) alone, so every schedule forms the same bits.
-// Reduction (Cody and Waite): pi/512 split into C1 (the double nearest) and
-// C2 (the double nearest pi/512 - C1), the product j C1 exact inside an FMA;
-// j comes from adding 1.5 * 2^52 inside the FMA that forms x * 512/pi, after
-// which the low bits of the sum's significand hold j (|x| < 2^45).
-// FULL (complex128): sin r through r^5, cos r through r^4 (first omitted terms
-// below 1e-21 and 2e-18).  Otherwise (complex64, whose state keeps 24 bits):
-// sin r through r^3, cos r through r^2 (below 3e-15 and 4e-12).
+// Reduction: r = x - j C1 in one FMA (the product exact), C1 the double
+// nearest pi/1024; the part of j pi/1024 that C1 misses, below |j| 1.2e-19 =
+// |x| 3.9e-17, is under half the unit in the last place of x itself, the
+// rounding x already carries (a second Cody-Waite term would refine r below
+// that).  j comes from adding 1.5 * 2^52 inside the FMA that forms
+// x * 1024/pi: the low bits of the sum's significand then hold j, for
+// |x| < 2^51 pi/1024 (about 2^42.6).
+// FULL (complex128): sin r through r^3, cos r through r^4 (first omitted terms
+// below 7.1e-17, under half a unit in the last place of 1, and 1.9e-20).
+// Otherwise (complex64, whose state keeps 24 bits): sin r as r, cos r through
+// r^2 (omitted below 6.1e-10 and 2.4e-13 per step: the first is a phase offset
+// of the order of the complex64 table's own 2^-31 fixed-point rounding).
 struct TdTurn {
-    double r;   // reduced angle, |r| <= pi/1024
-    double2 u;  // g exp(-i j pi/512) from the table
+    double r;   // reduced angle, |r| <= pi/2048
+    double2 u;  // g exp(-i j pi/1024) from the table
 };
 __device__ __forceinline__ TdTurn td_reduce(const double2 tw, double f, const double2* turns) {
-    const double C1 = 0x1.921fb54442d18p-8;   // pi/512 rounded to double
-    const double C2 = 0x1.1a62633145c07p-62;  // pi/512 - C1 rounded to double
+    const double C1 = 0x1.921fb54442d18p-9;   // pi/1024 rounded to double
     const double shifter = 0x1.8p52;          // 1.5 * 2^52: unit in the last place 1
     const double x = mad(f, tw.y, tw.x);
-    const double t = mad(x, 0x1.45f306dc9c883p+7, shifter);  // x * (512/pi) + shifter
+    const double t = mad(x, 0x1.45f306dc9c883p+8, shifter);  // x * (1024/pi) + shifter
     const double j = t - shifter;                              // exact
-    const unsigned idx = (unsigned)__double2loint(t) & (unsigned)(kTurns - 1);  // j mod 1024
-    double r = mad(-j, C1, x);
-    r = mad(-j, C2, r);
-    return TdTurn{r, turns[idx]};
+    const unsigned idx = (unsigned)__double2loint(t) & (unsigned)(kTurns - 1);  // j mod 2048
+    return TdTurn{mad(-j, C1, x), turns[idx]};
 }
 template <bool FULL>
 __device__ __forceinline__ double2 td_combine(const TdTurn& q) {
     const double r = q.r;
     const double r2 = r * r;
-    double ps = -1.0 / 6.0, pc = -0.5;
+    double sr = r;                              // sin r
+    double cr;                                  // cos r
     if constexpr (FULL) {
-        ps = mad(r2, 1.0 / 120.0, ps);
-        pc = mad(r2, 1.0 / 24.0, pc);
+        sr = mad(r * r2, -1.0 / 6.0, r);
+        cr = mad(r2, mad(r2, 1.0 / 24.0, -0.5), 1.0);
+    } else {
+        cr = mad(r2, -0.5, 1.0);
     }
-    const double sr = mad(r * r2, ps, r);   // sin r
-    const double cr = mad(r2, pc, 1.0);     // cos r
     const double2 u = q.u;
     // (u.x + i u.y)(cr - i sr)
     return make_double2(mad(u.x, cr, u.y * sr), mad(u.y, cr, -(u.x * sr)));
@@ -936,7 +939,8 @@ const void* pick_variant(int steps, int ppl, bool lds) {
         // beyond 6 steps per pass its loop outgrows the instruction cache
         if constexpr (V == Variant::TimeDep || V == Variant::ClosedTimeDep)
             return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxTdSteps>());
-        return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxSteps>());
+        else
+            return pick_steps<T, V, LAST, 1, true>(steps, std::make_integer_sequence<int, kMaxSteps>());
     }
     if (ppl == 2) {
         if constexpr (V != Variant::Single && V != Variant::Batch) return nullptr;
@@ -944,7 +948,8 @@ const void* pick_variant(int steps, int ppl, bool lds) {
     }
     if constexpr (V == Variant::TimeDep || V == Variant::ClosedTimeDep)
         return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxTdSteps>());
-    return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
+    else
+        return pick_steps<T, V, LAST, 1, false>(steps, std::make_integer_sequence<int, kMaxRegSteps>());
 }
 
 // Kernel of one instance of variant V (instantiates only that variant).

@@ -64,13 +64,13 @@ __global__ void td_table(const double* __restrict__ V0, const double* __restrict
         T[l] = make_double2(dt * (V0[l] + eps0) / hbar, dt * W[l] / hbar);
 }
 
-// The march's factors scale * exp(-i j pi/512), j = 0 .. kTurns-1 (j / 512 is
-// exact, so sincospi sees the angle without rounding).
+// The march's factors scale * exp(-i j pi/1024), j = 0 .. kTurns-1 (j / 1024
+// is exact, so sincospi sees the angle without rounding).
 __global__ void td_turns(double2* __restrict__ U, double scale) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= kTurns) return;
     double sn, cs;
-    sincospi((double)j / 512.0, &sn, &cs);
+    sincospi((double)j / 1024.0, &sn, &cs);
     U[j] = make_double2(scale * cs, -(scale * sn));
 }
 

@@ -172,7 +172,7 @@ def test_td_phase_factor_alone(dtype):
     """With a mass so large that every kinetic rotation rounds to the identity, a
     step is its phase factor alone: psi_n = psi_0 exp(-i sum_k (theta0 + f_k w)).
     Checked site by site against that closed form over angles of up to ~1e3 rad
-    of either sign (the angle-addition reduction, the 256-factor table with
+    of either sign (the angle-addition reduction, the factor table with
     negative indices, the short series) and against the oracle."""
     nx, ny = 130, 34
     rng = np.random.default_rng(51)
