@@ -109,11 +109,11 @@ const char* tsq_last_error(void);
  * schedule.  Host only; touches no device.
  * Periodic 2D meshes apply the rotations in a tangent form (see
  * tsq_evolve) and accept |dt| hbar / (2 m da^2) < 1 rad per step along each
- * axis (larger steps are far outside the product's accuracy anyway).
+ * axis; closed 2D meshes apply it to the half-step even factors and accept
+ * < 2 rad (larger steps are far outside the product's accuracy anyway).
  * Errors: TSQ_ERR_ARG (null, bad constant, order not 0/2/4), TSQ_ERR_SHAPE,
  * TSQ_ERR_DTYPE, TSQ_ERR_UNSUPPORTED (a 3D mesh with closed boundaries or
- * order 4; a periodic 2D time step beyond that angle).  *out is set only on
- * TSQ_OK. */
+ * order 4; a 2D time step beyond that angle).  *out is set only on TSQ_OK. */
 int tsq_plan_create(const tsq_problem* problem, tsq_plan** out);
 
 /* Free a plan (NULL is accepted). */
@@ -163,8 +163,10 @@ int tsq_evolve_passes(const tsq_plan* plan, int64_t steps, int64_t* passes, int3
  * eps_l = V_l + hbar^2/(m a^2) per axis) acts through exp(-i dt eps_l / hbar):
  * build that phase table exp(-i dt (V_l + eps0) / hbar) in FP64 from the device
  * array V_dev (nx*ny doubles) into the workspace `ws` of `ws_bytes` bytes
- * (device, 256-byte aligned), rounded to the plan's dtype (complex64: a hi + lo
- * pair of complex floats, exp = hi + lo to about 48 bits).
+ * (device, 256-byte aligned).  On 2D meshes the table also carries the
+ * cosines the tangent-form rotations leave out (see tsq_evolve).  complex128
+ * stores it in FP64; complex64 as two int32 fixed-point parts scaled by 2^30
+ * (8 bytes per site, about 31 bits each).
  * Records `ws`; tsq_evolve must be given the same workspace.
  * Errors: TSQ_ERR_ARG (null), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */
 int tsq_set_potential(tsq_plan* plan, const double* V_dev, void* ws, size_t ws_bytes,
@@ -175,9 +177,11 @@ int tsq_set_potential(tsq_plan* plan, const double* V_dev, void* ws, size_t ws_b
  * contiguous, 16-byte aligned): several steps are fused per read and write of
  * psi (the schedule's steps_per_pass), consecutive odd factors merged.  On
  * periodic 2D meshes the even and odd-y factors rotate in the tangent form
- * (a, b) <- (a + i t b, b + i t a), t = tan al, and the odd-x factor of each step
- * restores the product of the cosines; equal to the block exponentials in real
- * arithmetic.  steps == 0 returns TSQ_OK without a launch.
+ * (a, b) <- (a + i t b, b + i t a), t = tan al, and the phase factor and the
+ * odd-x factors opening and closing the evolution restore the product of the
+ * cosines; on closed 2D meshes the even factors rotate in the tangent form and
+ * the phase factor restores their cosines site by site.  Equal to the block
+ * exponentials in real arithmetic.  steps == 0 returns TSQ_OK without a launch.
  * Errors: TSQ_ERR_ARG (null, steps < 0, misaligned psi), TSQ_ERR_STATE (no
  * potential set, a different workspace, or a time-dependent table from
  * tsq_set_potential_td), TSQ_ERR_WORKSPACE, TSQ_ERR_DEVICE. */

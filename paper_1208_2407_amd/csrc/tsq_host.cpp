@@ -674,17 +674,21 @@ int tsq_plan_create(const tsq_problem* pr, tsq_plan** out) {
         u.oy2 = block_coef(dts[k], p->Jy, hb);
     }
     // Periodic 2D meshes rotate in the tangent form (tan al of the half and
-    // whole time step), which needs every angle well inside (-pi/2, pi/2).
-    if (!three_d && pr->bc == TSQ_BC_PERIODIC) {
+    // whole time step), closed ones their even factors (half step), which
+    // needs every such angle well inside (-pi/2, pi/2).
+    if (!three_d) {
+        const bool closed = pr->bc == TSQ_BC_CLOSED;
+        const double limit = closed ? 2.0 * kMaxAngle : kMaxAngle;  // on the whole-step angle
         for (int k = 0; k < p->nkinds; ++k) {
             const SubStep& u = p->kind[k];
-            if (std::fabs(u.ox2.al) >= kMaxAngle || std::fabs(u.oy2.al) >= kMaxAngle) {
+            if (std::fabs(u.ox2.al) >= limit || std::fabs(u.oy2.al) >= limit) {
                 delete p;
                 return fail(TSQ_ERR_UNSUPPORTED,
                             "|dt| hbar / (2 m da^2) = %g rad per step along %s is too large for the "
-                            "tangent-form rotation of periodic meshes (limit %g)",
+                            "tangent-form rotation of %s meshes (limit %g)",
                             std::max(std::fabs(u.ox2.al), std::fabs(u.oy2.al)),
-                            std::fabs(u.ox2.al) >= std::fabs(u.oy2.al) ? "x" : "y", kMaxAngle);
+                            std::fabs(u.ox2.al) >= std::fabs(u.oy2.al) ? "x" : "y",
+                            closed ? "closed" : "periodic", limit);
             }
         }
     }
@@ -792,9 +796,27 @@ int tsq_set_potential(tsq_plan* plan, const double* V, void* ws, size_t ws_bytes
     char* w = static_cast<char*>(ws);
     for (int k = 0; k < plan->nkinds; ++k) {
         const SubStep& u = plan->kind[k];
-        // periodic 2D meshes: the table carries a step's cosines (the march's
-        // tangent-form factors leave them out)
-        const double scale = std::exp(-0.5 * table_log(plan, k));
+        // 2D meshes: the table carries the cosines the march's tangent-form
+        // factors leave out, a step's on periodic meshes, the even factors'
+        // that pair the site on closed ones
+        tsq::TableScale scale;
+        if (!plan->three_d && plan->p.bc == TSQ_BC_CLOSED) {
+            const bool c128 = plan->p.dtype == TSQ_C128;
+            const double Lx = c128 ? tsq::log_sec2(tsq::tangent<double>(u.oxh))
+                                   : tsq::log_sec2(tsq::tangent<float>(u.oxh));
+            const double Ly = c128 ? tsq::log_sec2(tsq::tangent<double>(u.oyh))
+                                   : tsq::log_sec2(tsq::tangent<float>(u.oyh));
+            // two even x and two even y factors per step: cos^2 = exp(-log_sec2)
+            scale.g = std::exp(-(Lx + Ly));
+            scale.gx = std::exp(-Ly);
+            scale.gy = std::exp(-Lx);
+            scale.gxy = 1.0;
+            scale.nx = plan->p.nx;
+            scale.wx = (plan->p.nx & 1) ? plan->p.nx - 1 : -1;
+            scale.wy0 = (plan->p.ny & 1) ? (long long)(plan->p.ny - 1) * plan->p.nx : -1;
+        } else {
+            scale.g = std::exp(-0.5 * table_log(plan, k));
+        }
         hipError_t e = tsq::launch_phase_table(plan->p.dtype, V, w + u.off_ptab,
                                                (long long)plan->sites, u.dt, plan->eps0,
                                                plan->p.hbar, scale,

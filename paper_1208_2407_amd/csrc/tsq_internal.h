@@ -67,12 +67,22 @@ MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per
 // batched kernel, uploaded to device memory).  R = double (complex128) or
 // float (complex64).
 //
-// Two forms of the rotations.  Closed meshes apply every block exponential
-// in the delta form a' = a + (i s b - d a) (4 multiply-adds per site).
-// Periodic meshes use the tangent form (a, b) <- (a + i t b, b + i t a),
-// t = tan(al), which is sec(al) times the block exponential (2 multiply-adds
-// per site); every site of a periodic mesh meets each of a step's factors, so
-// the dropped cosines multiply every site alike and are restored elsewhere:
+// Two forms of the rotations: the delta form a' = a + (i s b - d a) (4
+// multiply-adds per site) and the tangent form (a, b) <- (a + i t b,
+// b + i t a), t = tan(al), which is sec(al) times the block exponential (2
+// multiply-adds per site).
+// Closed meshes apply the odd factors in the delta form and the four even
+// factors of a step in the tangent form (the delta form under a
+// time-dependent potential).  Between the first and the last even factor of
+// a step the only other operators are even y (even x) factors, which act
+// within columns (rows), and the diagonal phase; so the cosines the even
+// factors leave out, per site the product over the factors that pair it
+// (a site of the last column of an odd-width mesh has no even x partner, one
+// of the last row of an odd-height mesh no even y partner), come back exactly
+// as a per-site scale of the phase table.
+// Periodic meshes use the tangent form throughout; every site of a periodic
+// mesh meets each of a step's factors, so the dropped cosines multiply every
+// site alike and are restored elsewhere:
 //   * time-independent potentials: the phase table holds exp(-i phi) times the
 //     product g of a whole step's cosines (see phase_scale); stage 0 of a pass
 //     applies its odd x factor in the delta form with s' = t, d' = 0 (the
@@ -135,7 +145,9 @@ void delta_odd_x(double al, double L, R& xs, R& xd) {
 }
 // Log of the squared modulus a steady step's tangent factors multiply every
 // site by (odd x and y at tau = dt, two even x and two even y at dt/2); the
-// phase table of a periodic mesh holds exp(-i phi) * exp(-L/2).
+// phase table of a periodic mesh holds exp(-i phi) * exp(-L/2).  A closed
+// mesh's table holds exp(-i phi) times the cosines of the even factors that
+// pair the site (log_sec2 of the even tangents).
 template <class R>
 double step_log_sec2(const Coef64& oxh, const Coef64& oyh, const Coef64& ox2,
                      const Coef64& oy2) {
@@ -160,8 +172,14 @@ MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
     if (d.closed) {
         a.o1xs = (R)ox1.s; a.o1xd = (R)ox1.d; a.o1ys = (R)oy1.s; a.o1yd = (R)oy1.d;
         a.o2xs = (R)d.ox2.s; a.o2xd = (R)d.ox2.d; a.o2ys = (R)d.oy2.s; a.o2yd = (R)d.oy2.d;
-        a.ehxs = (R)d.oxh.s; a.ehxd = (R)d.oxh.d; a.ehys = (R)d.oyh.s; a.ehyd = (R)d.oyh.d;
-        a.c1xs = a.ehxs; a.c1xd = a.ehxd; a.c1ys = a.ehys; a.c1yd = a.ehyd;
+        a.c1xs = (R)d.oxh.s; a.c1xd = (R)d.oxh.d; a.c1ys = (R)d.oyh.s; a.c1yd = (R)d.oyh.d;
+        if (d.td) {
+            a.ehxs = a.c1xs; a.ehxd = a.c1xd; a.ehys = a.c1ys; a.ehyd = a.c1yd;
+        } else {
+            a.ehxs = tangent<R>(d.oxh);
+            a.ehys = tangent<R>(d.oyh);
+            a.ehxd = a.ehyd = R(0);
+        }
     } else {
         const R tex = tangent<R>(d.oxh), tey = tangent<R>(d.oyh);
         const double Le = 2.0 * log_sec2(tex) + 2.0 * log_sec2(tey);  // four even factors
@@ -233,8 +251,16 @@ bool march_variant_exists(int dtype, int steps, bool last, int pairs_per_lane, b
 
 // All launchers return hipSuccess or the launch error.
 // exp(-i dt (V + eps0) / hbar) times `scale` per site.
+// Per-site scale of the phase table: g, or on a closed mesh gx on the last
+// column (column wx >= 0: an odd width leaves it without an even x partner),
+// gy on the last row (from site wy0 >= 0: an odd height), gxy on both.
+struct TableScale {
+    double g = 1.0, gx = 1.0, gy = 1.0, gxy = 1.0;
+    long long nx = 1, wx = -1, wy0 = -1;
+};
 hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long sites,
-                              double dt, double eps0, double hbar, double scale, hipStream_t s);
+                              double dt, double eps0, double hbar, const TableScale& scale,
+                              hipStream_t s);
 // Table of the time-dependent potential V0 + f(t) W: per site the phase angle
 // theta0 = dt (V0 + eps0) / hbar and its modulation w = dt W / hbar, as a
 // double2 (16 B/site, both dtypes); step n's phase is exp(-i (theta0 + f_n w)).

@@ -330,11 +330,16 @@ __device__ __forceinline__ void pair_y_t(Row<R, SPL>& u, Row<R, SPL>& v, R t) {
     for (int i = 0; i < SPL; ++i) rot_pair_t(u.re[i], u.im[i], v.re[i], v.im[i], t);
 }
 
-// Even x-pairs in the tangent form (periodic meshes: every pair exists).
-template <class R, int SPL>
-__device__ __forceinline__ void even_x_t(Row<R, SPL>& w, R t) {
+// Even x-pairs in the tangent form (closed meshes: a zero tangent for a pair
+// that reaches beyond the wall).
+template <bool CLOSED, class R, int SPL>
+__device__ __forceinline__ void even_x_t(Row<R, SPL>& w, R t, const XPairs<SPL / 2, CLOSED>& m) {
 #pragma unroll
-    for (int p = 0; p < SPL / 2; ++p) rot_pair_t(w.re[2 * p], w.im[2 * p], w.re[2 * p + 1], w.im[2 * p + 1], t);
+    for (int p = 0; p < SPL / 2; ++p) {
+        bool ok = true;
+        if constexpr (CLOSED) ok = m.even[p];
+        rot_pair_t(w.re[2 * p], w.im[2 * p], w.re[2 * p + 1], w.im[2 * p + 1], pair_coef<CLOSED>(ok, t));
+    }
 }
 
 template <class PT, class R, int SPL>
@@ -415,11 +420,12 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // last pass applies only the closing odd factors.  With a time-dependent
 // potential (TD) the phase pair holds (theta0, w) per site and stage k forms
 // step k's factor from a.g[k] and `turns` (LDS).  Closed meshes rotate the
-// y-pairs that cross a wall with zero coefficients (`qk` is the pair stage k
-// completes; a wavefront-uniform test) and apply every factor in the delta
-// form; periodic meshes apply the tangent form, the odd x factors of stage 0
-// and of the closing stage in the delta form that restores the cosines the
-// phase factor does not (see MarchArgs).
+// pairs that cross a wall with zero coefficients (y: `qk` is the pair stage k
+// completes; a wavefront-uniform test) and apply the odd factors in the
+// delta form, the even factors in the tangent form (in the delta form under
+// a time-dependent potential); periodic meshes apply the tangent form, the
+// odd x factors of stage 0 and of the closing stage in the delta form that
+// restores the cosines the phase factor does not (see MarchArgs).
 template <int S, int K, bool CLOSED, bool TD, bool U4, class R, int SPL, class PT, class PhaseFn>
 __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
                                                const MarchArgs<R>& a,
@@ -437,14 +443,14 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
         if (k < S) {
             const int q = k == 2 ? 1 : 0;
             const PhasePair<PT, SPL> ph = phase(k);
-            even_x_t(o.f, a.u4.ext[q]);
-            even_x_t(o.g, a.u4.ext[q]);
+            even_x_t<CLOSED>(o.f, a.u4.ext[q], xm);
+            even_x_t<CLOSED>(o.g, a.u4.ext[q], xm);
             pair_y_t(o.f, o.g, a.u4.eyt[q]);
             phase_row(o.f, ph.f);
             phase_row(o.g, ph.g);
             pair_y_t(o.f, o.g, a.u4.eyt[q]);
-            even_x_t(o.f, a.u4.ext[q]);
-            even_x_t(o.g, a.u4.ext[q]);
+            even_x_t<CLOSED>(o.f, a.u4.ext[q], xm);
+            even_x_t<CLOSED>(o.g, a.u4.ext[q], xm);
         }
         return;
     }
@@ -468,8 +474,8 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
         pair_y_t(o.g, n.f, oys);
         if (k < S) {
             const PhasePair<PT, SPL> ph = phase(k);
-            even_x_t(o.f, a.ehxs);
-            even_x_t(o.g, a.ehxs);
+            even_x_t<CLOSED>(o.f, a.ehxs, xm);
+            even_x_t<CLOSED>(o.g, a.ehxs, xm);
             pair_y_t(o.f, o.g, a.ehys);
             if constexpr (TD) {
                 phase_rows_td(o.f, o.g, ph.f, ph.g, a.g[k], turns);
@@ -478,8 +484,8 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
                 phase_row(o.g, ph.g);
             }
             pair_y_t(o.f, o.g, a.ehys);
-            even_x_t(o.f, a.ehxs);
-            even_x_t(o.g, a.ehxs);
+            even_x_t<CLOSED>(o.f, a.ehxs, xm);
+            even_x_t<CLOSED>(o.g, a.ehxs, xm);
         }
         return;
     }
@@ -493,19 +499,28 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
     pair_y(o.g, n.f, oy_ok ? oys : R(0), oy_ok ? oyd : R(0));
     if (k < S) {
         const PhasePair<PT, SPL> ph = phase(k);
-        even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
-        even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
         const R eys = ey_ok ? a.ehys : R(0), eyd = ey_ok ? a.ehyd : R(0);
-        pair_y(o.f, o.g, eys, eyd);
         if constexpr (TD) {
+            even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
+            even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
+            pair_y(o.f, o.g, eys, eyd);
             phase_rows_td(o.f, o.g, ph.f, ph.g, a.g[k], turns);
+            pair_y(o.f, o.g, eys, eyd);
+            even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
+            even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
         } else {
+            // the even factors and the phase in the tangent form: the table
+            // restores their cosines site by site (see MarchArgs)
+            (void)eyd;
+            even_x_t<CLOSED>(o.f, a.ehxs, xm);
+            even_x_t<CLOSED>(o.g, a.ehxs, xm);
+            pair_y_t(o.f, o.g, eys);
             phase_row(o.f, ph.f);
             phase_row(o.g, ph.g);
+            pair_y_t(o.f, o.g, eys);
+            even_x_t<CLOSED>(o.f, a.ehxs, xm);
+            even_x_t<CLOSED>(o.g, a.ehxs, xm);
         }
-        pair_y(o.f, o.g, eys, eyd);
-        even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
-        even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
     }
 }
 

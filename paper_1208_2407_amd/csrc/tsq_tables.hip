@@ -12,9 +12,16 @@ struct C64 {};
 
 // ------------------------------------------------------------------ phase table of H0 (Sec. 2)
 
-// exp(-i phi_l) times `g` (the product of a step's cosines on periodic
-// meshes, else 1) for sites l = i, i + n/4... of each thread's four-site
-// groups: the four loads of V are issued before the four sines and cosines.
+// exp(-i phi_l) times the site's scale (the cosines the march's tangent-form
+// factors leave out; see TableScale) for sites l = i, i + n/4... of each
+// thread's four-site groups: the four loads of V are issued before the four
+// sines and cosines.
+__device__ __forceinline__ double site_scale(const TableScale& sc, long long l) {
+    if (sc.wx < 0 && sc.wy0 < 0) return sc.g;
+    const bool x = sc.wx >= 0 && l % sc.nx == sc.wx;
+    const bool y = sc.wy0 >= 0 && l >= sc.wy0;
+    return x ? (y ? sc.gxy : sc.gx) : (y ? sc.gy : sc.g);
+}
 template <class Store>
 __device__ __forceinline__ void phase_sites(const double* __restrict__ V, long long n, double dt,
                                             double eps0, double hbar, Store&& store) {
@@ -39,8 +46,9 @@ __device__ __forceinline__ void phase_sites(const double* __restrict__ V, long l
 }
 
 __global__ void phase_table_c128(const double* __restrict__ V, double2* __restrict__ P,
-                                 long long n, double dt, double eps0, double hbar, double g) {
+                                 long long n, double dt, double eps0, double hbar, TableScale sc) {
     phase_sites(V, n, dt, eps0, hbar, [&](long long l, double c, double s) {
+        const double g = site_scale(sc, l);
         P[l] = make_double2(g * c, -(g * s));
     });
 }
@@ -48,8 +56,9 @@ __global__ void phase_table_c128(const double* __restrict__ V, double2* __restri
 // complex64: cos(phi) and -sin(phi) as 32-bit fixed point, value * 2^30
 // rounded to nearest (|value| <= 1, so 2^30 fits; error <= 2^-31 per part).
 __global__ void phase_table_c64(const double* __restrict__ V, int2* __restrict__ P,
-                                long long n, double dt, double eps0, double hbar, double g) {
+                                long long n, double dt, double eps0, double hbar, TableScale sc) {
     phase_sites(V, n, dt, eps0, hbar, [&](long long l, double c, double s) {
+        const double g = site_scale(sc, l);
         P[l] = make_int2(__double2int_rn(g * c * 0x1p30), __double2int_rn(-(g * s) * 0x1p30));
     });
 }
@@ -331,7 +340,8 @@ observables_final(const double* __restrict__ partial, int nblocks, double* __res
 }  // namespace
 
 hipError_t launch_phase_table(int dtype, const double* V, void* ptab, long long sites,
-                              double dt, double eps0, double hbar, double scale, hipStream_t s) {
+                              double dt, double eps0, double hbar, const TableScale& scale,
+                              hipStream_t s) {
     const int threads = 256;
     long long want = (sites + threads - 1) / threads;
     const int blocks = (int)(want < 8192 ? want : 8192);

@@ -56,6 +56,8 @@ def problem(**kw):
     # periodic 2D meshes rotate in the tangent form: |dt| hbar / (2 m da^2) < 1 rad
     (dict(dt=2.0), -7), (dict(dt=-2.0), -7), (dict(dt=0.3, dy=0.3), -7),
     (dict(dt=3.2, order=4), -7),   # its longest sub-step, |1-4p| dt, is 1.05 rad
+    # closed 2D meshes rotate their half-step even factors in the tangent form: < 2 rad
+    (dict(dt=4.2, bc=1), -7), (dict(dt=0.6, dy=0.3, bc=1), -7),
 ])
 def test_plan_create_rejects(kw, status):
     with pytest.raises(tsq.TsqError) as ei:
@@ -77,9 +79,10 @@ def test_plan_create_accepts_negative_dt_and_reports_workspace():
 
 
 def test_large_steps_stay_allowed_where_no_tangent_form_runs():
-    # closed meshes and 3D meshes rotate in the delta form: any finite dt
-    # order 4: the longest sub-step is |1-4p| dt = 0.66 dt
-    for kw in (dict(dt=2.0, bc=1), dict(dt=2.0, nz=4), dict(dt=1.99), dict(dt=2.5, order=4)):
+    # 3D meshes rotate in the delta form: any finite dt; closed 2D meshes take
+    # the tangent form for the half-step even factors only (whole-step angle
+    # below 2 rad); order 4: the longest sub-step is |1-4p| dt = 0.66 dt
+    for kw in (dict(dt=3.9, bc=1), dict(dt=2.0, nz=4), dict(dt=1.99), dict(dt=2.5, order=4)):
         h = tsq.tsq_plan_create(problem(**kw))
         tsq.tsq_plan_destroy(h)
 
