@@ -173,6 +173,16 @@ double table_log(const tsq_plan* p, int k) {
                                   : tsq::step_log_sec2<float>(u.oxh, u.oyh, u.ox2, u.oy2);
 }
 
+// Closed 2D meshes: log(1 + t^2) of the even x and y tangents of sub-step
+// kind k as the march rounds them (the squared secant each even factor
+// multiplies a paired site by).
+void closed_even_logs(const tsq_plan* p, int k, double& Lx, double& Ly) {
+    const SubStep& u = p->kind[k];
+    const bool c128 = p->p.dtype == TSQ_C128;
+    Lx = c128 ? tsq::log_sec2(tsq::tangent<double>(u.oxh)) : tsq::log_sec2(tsq::tangent<float>(u.oxh));
+    Ly = c128 ? tsq::log_sec2(tsq::tangent<double>(u.oyh)) : tsq::log_sec2(tsq::tangent<float>(u.oyh));
+}
+
 // Pass sizes as runs of (steps per pass, repeat): S steps each, the remainder
 // in the last pass.  An odd pass count would leave the result in the second
 // buffer, so the last pass holding more than one step is split in two; if no
@@ -801,11 +811,8 @@ int tsq_set_potential(tsq_plan* plan, const double* V, void* ws, size_t ws_bytes
         // that pair the site on closed ones
         tsq::TableScale scale;
         if (!plan->three_d && plan->p.bc == TSQ_BC_CLOSED) {
-            const bool c128 = plan->p.dtype == TSQ_C128;
-            const double Lx = c128 ? tsq::log_sec2(tsq::tangent<double>(u.oxh))
-                                   : tsq::log_sec2(tsq::tangent<float>(u.oxh));
-            const double Ly = c128 ? tsq::log_sec2(tsq::tangent<double>(u.oyh))
-                                   : tsq::log_sec2(tsq::tangent<float>(u.oyh));
+            double Lx, Ly;
+            closed_even_logs(plan, k, Lx, Ly);
             // two even x and two even y factors per step: cos^2 = exp(-log_sec2)
             scale.g = std::exp(-(Lx + Ly));
             scale.gx = std::exp(-Ly);
@@ -839,8 +846,15 @@ int tsq_set_potential_td(tsq_plan* plan, const double* V0, const double* W, void
     int rc = check_ws(plan, ws, ws_bytes);
     if (rc) return rc;
     char* w = static_cast<char*>(ws);
-    // periodic meshes: the factors carry a step's cosines, as the static table does
-    const double scale = std::exp(-0.5 * table_log(plan, 0));
+    // the factors carry the cosines the tangent-form rotations leave out, as the
+    // static table does: a step's on periodic meshes, the four even factors' on
+    // closed ones (the march rescales the last odd column and row)
+    double scale = std::exp(-0.5 * table_log(plan, 0));
+    if (plan->p.bc == TSQ_BC_CLOSED) {
+        double Lx, Ly;
+        closed_even_logs(plan, 0, Lx, Ly);
+        scale = std::exp(-(Lx + Ly));
+    }
     hipError_t e = tsq::launch_td_table(V0, W, w + plan->kind[0].off_ptab, w + plan->off_turns,
                                         (long long)plan->sites, plan->kind[0].dt, plan->eps0,
                                         plan->p.hbar, scale, static_cast<hipStream_t>(stream));

@@ -72,14 +72,15 @@ MarchGeometry march_geometry(int nx, int ny, int steps, bool last, int pairs_per
 // b + i t a), t = tan(al), which is sec(al) times the block exponential (2
 // multiply-adds per site).
 // Closed meshes apply the odd factors in the delta form and the four even
-// factors of a step in the tangent form (the delta form under a
-// time-dependent potential).  Between the first and the last even factor of
-// a step the only other operators are even y (even x) factors, which act
+// factors of a step in the tangent form.  Between the first and the last even
+// factor of a step the only other operators are even y (even x) factors, which act
 // within columns (rows), and the diagonal phase; so the cosines the even
 // factors leave out, per site the product over the factors that pair it
 // (a site of the last column of an odd-width mesh has no even x partner, one
 // of the last row of an odd-height mesh no even y partner), come back exactly
-// as a per-site scale of the phase table.
+// as a per-site scale of the phase table (time-dependent potentials: the
+// shared factors carry the interior's scale and the march multiplies the
+// last odd column's and row's factors by kxw, kyw).
 // Periodic meshes use the tangent form throughout; every site of a periodic
 // mesh meets each of a step's factors, so the dropped cosines multiply every
 // site alike and are restored elsewhere:
@@ -120,6 +121,7 @@ struct MarchArgs {
     R ehxs, ehxd, ehys, ehyd;  // even factors, tau = dt/2
     R c1xs, c1xd, c1ys, c1yd;  // odd factors closing the evolution, tau = dt/2
     double g[kMaxSteps];       // time-dependent potential: f_n of step k of the pass
+    double kxw, kyw;           // closed, time-dependent: scale of the last odd column, row
     Order4Coefs<R> u4;         // fourth order in one pass per step
 };
 
@@ -173,14 +175,15 @@ MarchArgs<R> make_march_args(const PassDesc& d, const MarchGeometry& g) {
         a.o1xs = (R)ox1.s; a.o1xd = (R)ox1.d; a.o1ys = (R)oy1.s; a.o1yd = (R)oy1.d;
         a.o2xs = (R)d.ox2.s; a.o2xd = (R)d.ox2.d; a.o2ys = (R)d.oy2.s; a.o2yd = (R)d.oy2.d;
         a.c1xs = (R)d.oxh.s; a.c1xd = (R)d.oxh.d; a.c1ys = (R)d.oyh.s; a.c1yd = (R)d.oyh.d;
-        if (d.td) {
-            a.ehxs = a.c1xs; a.ehxd = a.c1xd; a.ehys = a.c1ys; a.ehyd = a.c1yd;
-        } else {
-            a.ehxs = tangent<R>(d.oxh);
-            a.ehys = tangent<R>(d.oyh);
-            a.ehxd = a.ehyd = R(0);
-        }
+        a.ehxs = tangent<R>(d.oxh);
+        a.ehys = tangent<R>(d.oyh);
+        a.ehxd = a.ehyd = R(0);
+        // the last column (row) of an odd width (height) has no even x (y)
+        // partner: 1 / cos^2 of that factor over the interior's scale
+        a.kxw = std::exp(log_sec2(a.ehxs));
+        a.kyw = std::exp(log_sec2(a.ehys));
     } else {
+        a.kxw = a.kyw = 1.0;
         const R tex = tangent<R>(d.oxh), tey = tangent<R>(d.oyh);
         const double Le = 2.0 * log_sec2(tex) + 2.0 * log_sec2(tey);  // four even factors
         a.ehxs = tex;

@@ -161,13 +161,23 @@ __device__ __forceinline__ double2 td_combine(const TdTurn& q) {
     return make_double2(mad(u.x, cr, u.y * sr), mad(u.y, cr, -(u.x * sr)));
 }
 
-// Apply the factor: complex128 in place; complex64 widened to FP64,
-// multiplied, rounded once.
-__device__ __forceinline__ void apply_phase_td(double& re, double& im, const TdTurn& q) {
-    apply_phase(re, im, td_combine<true>(q));
+// Apply the factor times the site's scale k (closed meshes; SCALE = false:
+// k = 1): complex128 in place; complex64 widened to FP64, multiplied, rounded
+// once.
+template <bool SCALE>
+__device__ __forceinline__ double2 td_factor(const double2 p, double k) {
+    if constexpr (SCALE)
+        return make_double2(p.x * k, p.y * k);
+    else
+        return (void)k, p;
 }
-__device__ __forceinline__ void apply_phase_td(float& re, float& im, const TdTurn& q) {
-    const double2 p = td_combine<false>(q);
+template <bool SCALE>
+__device__ __forceinline__ void apply_phase_td(double& re, double& im, const TdTurn& q, double k) {
+    apply_phase(re, im, td_factor<SCALE>(td_combine<true>(q), k));
+}
+template <bool SCALE>
+__device__ __forceinline__ void apply_phase_td(float& re, float& im, const TdTurn& q, double k) {
+    const double2 p = td_factor<SCALE>(td_combine<false>(q), k);
     const double r = re, i = im;
     re = (float)mad(r, p.x, -(i * p.y));
     im = (float)mad(r, p.y, i * p.x);
@@ -255,6 +265,7 @@ struct XPairs {
     bool even[PPL];      // (x, x+1) of pair p
     bool inner[PPL];     // (x+1, x+2) inside the lane, p < PPL-1
     bool left, right;    // odd pairs shared with the neighbouring lanes
+    double kx[2 * PPL];  // time-dependent phase: the site's column scale (last odd column)
 };
 template <int PPL>
 struct XPairs<PPL, false> {};
@@ -349,10 +360,12 @@ __device__ __forceinline__ void phase_row(Row<R, SPL>& w, const PT* p) {
 }
 
 // Both rows of a pair: every site's reduction and table read first, so the
-// LDS reads are in flight together, then the factors.
-template <class R, int SPL>
+// LDS reads are in flight together, then the factors.  SCALE (closed meshes):
+// site i of row a (b) takes the scale kx[i] * ka (kx[i] * kb).
+template <bool SCALE, class R, int SPL>
 __device__ __forceinline__ void phase_rows_td(Row<R, SPL>& a, Row<R, SPL>& b, const double2* pa,
-                                              const double2* pb, double f, const double2* turns) {
+                                              const double2* pb, double f, const double2* turns,
+                                              const double* kx, double ka, double kb) {
     TdTurn qa[SPL], qb[SPL];
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
@@ -361,8 +374,8 @@ __device__ __forceinline__ void phase_rows_td(Row<R, SPL>& a, Row<R, SPL>& b, co
     }
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
-        apply_phase_td(a.re[i], a.im[i], qa[i]);
-        apply_phase_td(b.re[i], b.im[i], qb[i]);
+        apply_phase_td<SCALE>(a.re[i], a.im[i], qa[i], SCALE ? kx[i] * ka : 1.0);
+        apply_phase_td<SCALE>(b.re[i], b.im[i], qb[i], SCALE ? kx[i] * kb : 1.0);
     }
 }
 
@@ -411,6 +424,48 @@ __device__ __forceinline__ int wrap(long long v, int n) {
     return (int)(m < 0 ? m + n : m);
 }
 
+// Stage k on a closed mesh (see pipeline_stage): the odd factors in the delta
+// form, the even factors in the tangent form with the phase factor restoring
+// their cosines site by site (see MarchArgs).  A pair that reaches beyond a
+// wall rotates with zero coefficients (x: per lane; y: a wavefront-uniform
+// choice, no branch).
+template <int S, bool TD, class R, int SPL, class PhaseFn>
+__device__ __forceinline__ void closed_stage(int k, PairRows<R, SPL>& o, PairRows<R, SPL>& n,
+                                             const MarchArgs<R>& a, const XPairs<SPL / 2, true>& xm,
+                                             int qk, bool rev, const double2* turns, PhaseFn&& phase,
+                                             R oxs, R oxd, R oys, R oyd) {
+    // odd y-pair: rows (2qk+1, 2qk+2) marching down, (2qk-1, 2qk) marching up;
+    // even y-pair of o: rows (2qk, 2qk+1)
+    const bool oy_ok = rev ? (qk >= 1 && 2 * qk < a.ny) : (qk >= 0 && 2 * qk + 2 < a.ny);
+    const bool ey_ok = qk >= 0 && 2 * qk + 1 < a.ny;
+    odd_x<true>(o.g, oxs, oxd, xm);
+    odd_x<true>(n.f, oxs, oxd, xm);
+    pair_y(o.g, n.f, oy_ok ? oys : R(0), oy_ok ? oyd : R(0));
+    if (k < S) {
+        const auto ph = phase(k);
+        const R eyt = ey_ok ? a.ehys : R(0);
+        even_x_t<true>(o.f, a.ehxs, xm);
+        even_x_t<true>(o.g, a.ehxs, xm);
+        pair_y_t(o.f, o.g, eyt);
+        if constexpr (TD) {
+            // the shared factors carry the cosines of a site with both even
+            // partners; the last column (row) of an odd width (height) takes
+            // the scale of the factor it sits out of
+            const int rf = rev ? 2 * qk + 1 : 2 * qk, rg = rev ? 2 * qk : 2 * qk + 1;
+            const bool odd_h = (a.ny & 1) != 0;
+            const double kf = (odd_h && rf == a.ny - 1) ? a.kyw : 1.0;
+            const double kg = (odd_h && rg == a.ny - 1) ? a.kyw : 1.0;
+            phase_rows_td<true>(o.f, o.g, ph.f, ph.g, a.g[k], turns, xm.kx, kf, kg);
+        } else {
+            phase_row(o.f, ph.f);
+            phase_row(o.g, ph.g);
+        }
+        pair_y_t(o.f, o.g, eyt);
+        even_x_t<true>(o.f, a.ehxs, xm);
+        even_x_t<true>(o.g, a.ehxs, xm);
+    }
+}
+
 // Stage k of the S-stage pipeline.  `o` is the older row pair, the one stage
 // k completes; `n` is the newer pair right behind it, just finished by stage
 // k-1 (or just loaded, for k = 0).  Stage k applies the odd factors on the
@@ -422,8 +477,8 @@ __device__ __forceinline__ int wrap(long long v, int n) {
 // step k's factor from a.g[k] and `turns` (LDS).  Closed meshes rotate the
 // pairs that cross a wall with zero coefficients (y: `qk` is the pair stage k
 // completes; a wavefront-uniform test) and apply the odd factors in the
-// delta form, the even factors in the tangent form (in the delta form under
-// a time-dependent potential); periodic meshes apply the tangent form, the
+// delta form, the even factors in the tangent form; periodic meshes apply the
+// tangent form, the
 // odd x factors of stage 0 and of the closing stage in the delta form that
 // restores the cosines the phase factor does not (see MarchArgs).
 template <int S, int K, bool CLOSED, bool TD, bool U4, class R, int SPL, class PT, class PhaseFn>
@@ -474,53 +529,21 @@ __device__ __forceinline__ void pipeline_stage(int k, PairRows<R, SPL>& o, PairR
         pair_y_t(o.g, n.f, oys);
         if (k < S) {
             const PhasePair<PT, SPL> ph = phase(k);
-            even_x_t<CLOSED>(o.f, a.ehxs, xm);
-            even_x_t<CLOSED>(o.g, a.ehxs, xm);
+            even_x_t<false>(o.f, a.ehxs, xm);
+            even_x_t<false>(o.g, a.ehxs, xm);
             pair_y_t(o.f, o.g, a.ehys);
             if constexpr (TD) {
-                phase_rows_td(o.f, o.g, ph.f, ph.g, a.g[k], turns);
+                phase_rows_td<false>(o.f, o.g, ph.f, ph.g, a.g[k], turns, nullptr, 1.0, 1.0);
             } else {
                 phase_row(o.f, ph.f);
                 phase_row(o.g, ph.g);
             }
             pair_y_t(o.f, o.g, a.ehys);
-            even_x_t<CLOSED>(o.f, a.ehxs, xm);
-            even_x_t<CLOSED>(o.g, a.ehxs, xm);
+            even_x_t<false>(o.f, a.ehxs, xm);
+            even_x_t<false>(o.g, a.ehxs, xm);
         }
-        return;
-    }
-    // odd y-pair: rows (2qk+1, 2qk+2) marching down, (2qk-1, 2qk) marching up
-    const bool oy_ok = !CLOSED || (rev ? (qk >= 1 && 2 * qk < a.ny) : (qk >= 0 && 2 * qk + 2 < a.ny));
-    const bool ey_ok = !CLOSED || (qk >= 0 && 2 * qk + 1 < a.ny);
-    odd_x<CLOSED>(o.g, oxs, oxd, xm);
-    odd_x<CLOSED>(n.f, oxs, oxd, xm);
-    // closed meshes: a y-pair reaching outside the mesh rotates with zero
-    // coefficients (a wavefront-uniform choice, no branch)
-    pair_y(o.g, n.f, oy_ok ? oys : R(0), oy_ok ? oyd : R(0));
-    if (k < S) {
-        const PhasePair<PT, SPL> ph = phase(k);
-        const R eys = ey_ok ? a.ehys : R(0), eyd = ey_ok ? a.ehyd : R(0);
-        if constexpr (TD) {
-            even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
-            even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
-            pair_y(o.f, o.g, eys, eyd);
-            phase_rows_td(o.f, o.g, ph.f, ph.g, a.g[k], turns);
-            pair_y(o.f, o.g, eys, eyd);
-            even_x<CLOSED>(o.f, a.ehxs, a.ehxd, xm);
-            even_x<CLOSED>(o.g, a.ehxs, a.ehxd, xm);
-        } else {
-            // the even factors and the phase in the tangent form: the table
-            // restores their cosines site by site (see MarchArgs)
-            (void)eyd;
-            even_x_t<CLOSED>(o.f, a.ehxs, xm);
-            even_x_t<CLOSED>(o.g, a.ehxs, xm);
-            pair_y_t(o.f, o.g, eys);
-            phase_row(o.f, ph.f);
-            phase_row(o.g, ph.g);
-            pair_y_t(o.f, o.g, eys);
-            even_x_t<CLOSED>(o.f, a.ehxs, xm);
-            even_x_t<CLOSED>(o.g, a.ehxs, xm);
-        }
+    } else {
+        closed_stage<S, TD>(k, o, n, a, xm, qk, rev, turns, phase, oxs, oxd, oys, oyd);
     }
 }
 
@@ -639,6 +662,8 @@ __device__ __forceinline__ void march_tile(const MarchArgs<typename T::R>& a, in
         }
         xm.left = in(xu0 - 1) && in(xu0);
         xm.right = in(xu0 + SPL - 1) && in(xu0 + SPL);
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) xm.kx[i] = ((nx & 1) && xu0 + i == nx - 1) ? a.kxw : 1.0;
     }
     // Closed meshes: a site outside the mesh loads any site inside (its column
     // and row clamped to the mesh) instead of a zero, since no rotation lets

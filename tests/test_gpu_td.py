@@ -80,6 +80,27 @@ def test_td_closed_meshes(shape, S, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_td_closed_odd_sides_long_run(dtype):
+    """Odd width and height between walls: the shared factors carry the
+    interior's even-factor cosines and the march rescales the last column and
+    row (no even partner there).  A wrong scale would grow step after step:
+    240 driven steps against the oracle, and the norm."""
+    nx, ny = 77, 45
+    psi0 = wl.random_state(nx, ny, 73)
+    V0 = wl.random_potential(nx, ny, 74, scale=0.5)
+    W = wl.random_potential(nx, ny, 75, scale=0.7)
+    f = np.sin(0.05 * np.arange(240)) * 1.3
+    want = oracle.evolve_td(as_input(psi0, dtype), V0, W, f, 0.11, bc="closed", **ANISO)
+    got = gpu_evolve_td(psi0, V0, W, f, 0.11, dtype, steps_per_pass=4, bc="closed", **ANISO)
+    err = rel_l2(got, want)
+    n0 = float(np.sum(np.abs(as_input(psi0, dtype).astype(np.complex128)) ** 2))
+    n1 = float(np.sum(np.abs(got.astype(np.complex128)) ** 2))
+    log(f"  td closed odd sides 240 steps {dtype}: rel L2 {err:.3e}, norm drift {n1 - n0:.3e}")
+    assert err <= (1e-11 if dtype == "c128" else 2e-5)
+    assert abs(n1 - n0) <= (1e-12 if dtype == "c128" else 1e-5) * n0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_td_closed_schedule_does_not_change_a_bit(dtype):
     nx, ny = 131, 67
     psi0 = wl.random_state(nx, ny, 80)
