@@ -393,13 +393,18 @@ def profile_mode(p, psi0, V, args) -> int:
 def sweep_mode(p, psi0, V, args) -> int:
     """Every candidate schedule of the tuner (1-8 steps per pass) for
     exactly --profile-passes passes after a warm-up, each timed with HIP events
-    on the current stream; one JSON line per dtype and schedule.  Run under
-    rocprofv3 --pmc it also gives the HBM counters of every schedule."""
+    on the current stream, then for twice as many: the difference is the time
+    of steady passes alone (the first and the closing pass, which differ, drop
+    out).  One JSON line per dtype and schedule.  Run under rocprofv3 --pmc it
+    also gives the HBM counters of every schedule."""
     import torch
     import paper_1208_2407_amd as tsq
     from paper_1208_2407_amd import autotune
 
     cands = list(autotune.DEFAULT_CANDIDATES)
+    if ":" in args.schedule:  # sweep:ROWS, every candidate at that segment height
+        rows = int(args.schedule.split(":", 1)[1])
+        cands = [(c[0], rows, c[2], c[3]) for c in cands]
     stream = torch.cuda.current_stream()
     # reference copy of known size (1 GiB read + 1 GiB written) to scale the counters
     src = torch.empty(2**27, dtype=torch.float64, device="cuda")
@@ -418,25 +423,36 @@ def sweep_mode(p, psi0, V, args) -> int:
             plan.set_schedule(*sched)
             S = sched[0]
             plan.evolve(psi, 2 * S)
+            def timed(steps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                plan.evolve(psi, steps)
+                e1.record(stream)
+                e1.synchronize()
+                return e0.elapsed_time(e1) * 1e-3
+
             steps = S * args.profile_passes
             passes = plan.passes(steps)[0]
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            plan.evolve(psi, steps)
-            e1.record(stream)
-            e1.synchronize()
-            sec = e0.elapsed_time(e1) * 1e-3
+            sec = timed(steps)
             pass_s = sec / passes
+            # twice the passes: the difference holds steady passes only
+            passes2 = plan.passes(2 * steps)[0]
+            steady_s = max(timed(2 * steps) - sec, 0.0) / max(passes2 - passes, 1)
             print(json.dumps({"sweep": True, "dtype": d, "schedule": list(sched),
                               "kernel_hash": kernel_hash(), "mesh": [p.nx, p.ny],
                               "steps": steps, "passes": passes,
                               "avg_pass_us": round(pass_s * 1e6, 2),
+                              "steady_pass_us": round(steady_s * 1e6, 2),
                               "us_per_step": round(sec / steps * 1e6, 3),
                               "site_steps_per_s": p.nx * p.ny * steps / sec,
+                              "steady_site_steps_per_s": (p.nx * p.ny * S / steady_s
+                                                          if steady_s > 0 else None),
                               "algorithmic_bytes_per_launch": alg,
                               "frac": round(alg / pass_s / 1e9 / HBM_PEAK_GBS, 4),
+                              "steady_frac": (round(alg / steady_s / 1e9 / HBM_PEAK_GBS, 4)
+                                              if steady_s > 0 else None),
                               "eff_frac_one_pass_per_step": round(
                                   p.nx * p.ny * steps / sec * alg / (p.nx * p.ny) / 1e9
                                   / HBM_PEAK_GBS, 3)}), flush=True)
@@ -774,7 +790,8 @@ def main() -> int:
                          "dtype run exactly this many fused passes under --schedule, plus one "
                          "device copy of 1 GiB (known bytes) to scale the HBM counters; prints "
                          "a short JSON and exits.  With --schedule sweep: every candidate "
-                         "schedule, each timed")
+                         "schedule, each timed (--schedule sweep:ROWS: at segments of ROWS "
+                         "rows)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="default run: skip the batch")
@@ -832,7 +849,7 @@ def main() -> int:
         log("generating inputs on the device")
         psi0 = wl.initial_state(p, device="cuda", dtype=torch.complex64)
         V = wl.potential(p, device="cuda")
-        if args.profile_passes and args.schedule == "sweep":
+        if args.profile_passes and args.schedule.startswith("sweep"):
             return sweep_mode(p, psi0, V, args)
         if args.profile_passes:
             return profile_mode(p, psi0, V, args)
@@ -893,7 +910,7 @@ def main() -> int:
     psi0 = wl.initial_state(p, device="cuda")
     V = wl.potential(p, device="cuda")
     torch.cuda.synchronize()
-    if args.profile_passes and args.schedule == "sweep":
+    if args.profile_passes and args.schedule.startswith("sweep"):
         return sweep_mode(p, psi0, V, args)
     if args.profile_passes:
         return profile_mode(p, psi0, V, args)
